@@ -1,0 +1,184 @@
+"""ctypes binding of the FP64 CPU oracle (``lbm_oracle.c``). Test infrastructure only.
+
+Array conventions follow the C side: structure of arrays, x fastest.
+  F   (19, nz, ny, nx)  post-stream auxiliary populations fbar_i
+  b   (6, nz, ny, nx)   auxiliary variance bbar, components xx yy zz xy xz yz
+  rho (nz, ny, nx), u (3, nz, ny, nx), T (nz, ny, nx)
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib_path():
+    return _build.LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build(force=False)
+        _lib = C.CDLL(_build.LIB)
+        d, i, l = C.c_double, C.c_int, C.c_long
+        P = C.POINTER(C.c_double)
+        _lib.orc_feq.argtypes = [d, d, d, d, P]
+        _lib.orc_beq.argtypes = [d, d, d, d, P]
+        _lib.orc_table_m.argtypes = [P]
+        _lib.orc_forcing.argtypes = [P, P, P]
+        _lib.orc_velocity_set.argtypes = [C.POINTER(C.c_int), P]
+        _lib.orc_gradient.argtypes = [i, i, i, P, i, P]
+        _lib.orc_init.argtypes = [i, i, i, P, P, P, P, P]
+        _lib.orc_step.argtypes = [i, i, i, d, i, P, P, P, l]
+        _lib.orc_step.restype = i
+        _lib.orc_moments.argtypes = [i, i, i, d, i, P, P, P, P, P, P]
+        _lib.orc_moments.restype = i
+        _lib.orc_forcing_moments.argtypes = [i, i, i, d, i, P, P, P, P, P]
+        _lib.orc_forcing_moments.restype = i
+        _lib.orc_invariants.argtypes = [i, i, i, P, P, P]
+        _lib.orc_step_sites.argtypes = [i, i, i, d, i, P, P, P, l, C.POINTER(C.c_long), P, P]
+        _lib.orc_step_sites.restype = i
+    return _lib
+
+
+def _p(a):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def velocity_set():
+    """(e, w): the 19 velocities as int array (19, 3) and the weights (19,)."""
+    e = np.zeros((19, 3), dtype=np.int32)
+    w = np.zeros(19)
+    _load().orc_velocity_set(e.ctypes.data_as(C.POINTER(C.c_int)), _p(w))
+    return e, w
+
+
+def feq(rho, ux, uy, uz):
+    out = np.zeros(19)
+    _load().orc_feq(float(rho), float(ux), float(uy), float(uz), _p(out))
+    return out
+
+
+def beq(ux, uy, uz, T):
+    out = np.zeros(6)
+    _load().orc_beq(float(ux), float(uy), float(uz), float(T), _p(out))
+    return out
+
+
+def table_m():
+    m = np.zeros((19, 19))
+    _load().orc_table_m(_p(m))
+    return m
+
+
+def forcing(Fv, S):
+    """Phi_i from the force F (3,) and second-moment source S (6,: xx yy zz xy xz yz)."""
+    Fv, S = _f64(Fv), _f64(S)
+    out = np.zeros(19)
+    _load().orc_forcing(_p(Fv), _p(S), _p(out))
+    return out
+
+
+def gradient(phi, axis):
+    """Isotropic D3Q19 finite difference of a periodic field phi (nz, ny, nx) along axis 0=x."""
+    phi = _f64(phi)
+    nz, ny, nx = phi.shape
+    out = np.zeros_like(phi)
+    _load().orc_gradient(nx, ny, nz, _p(phi), int(axis), _p(out))
+    return out
+
+
+MODES = {"thermal": 0, "iso": 1}
+
+
+class OracleLattice:
+    """A periodic nx*ny*nz lattice stepped by the oracle, state held in numpy arrays."""
+
+    def __init__(self, nx, ny, nz, tau, mode="thermal", T_field=None):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.n = self.nx * self.ny * self.nz
+        self.tau = float(tau)
+        self.mode = MODES[mode]
+        shape = (self.nz, self.ny, self.nx)
+        self.F = np.zeros((19,) + shape)
+        self.b = np.zeros((6,) + shape)
+        if T_field is None:
+            T_field = np.zeros(shape)
+        self.T_field = _f64(np.broadcast_to(T_field, shape))
+        self.steps = 0
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def init(self, rho, u, T):
+        rho = _f64(np.broadcast_to(rho, self.shape))
+        u = _f64(np.broadcast_to(u, (3,) + self.shape))
+        T = _f64(np.broadcast_to(T, self.shape))
+        if self.mode == 1:
+            self.T_field = T.copy()
+        _load().orc_init(self.nx, self.ny, self.nz, _p(rho), _p(u), _p(T), _p(self.F), _p(self.b))
+        self.steps = 0
+
+    def set_state(self, F, b):
+        self.F = _f64(F).reshape((19,) + self.shape).copy()
+        self.b = _f64(b).reshape((6,) + self.shape).copy()
+
+    def state(self):
+        return self.F.copy(), self.b.copy()
+
+    def step(self, n=1):
+        rc = _load().orc_step(self.nx, self.ny, self.nz, self.tau, self.mode, _p(self.T_field),
+                              _p(self.F), _p(self.b), int(n))
+        if rc != 0:
+            raise MemoryError("oracle step failed")
+        self.steps += int(n)
+
+    def moments(self):
+        rho = np.zeros(self.shape)
+        u = np.zeros((3,) + self.shape)
+        T = np.zeros(self.shape)
+        rc = _load().orc_moments(self.nx, self.ny, self.nz, self.tau, self.mode, _p(self.T_field),
+                                 _p(self.F), _p(self.b), _p(rho), _p(u), _p(T))
+        if rc != 0:
+            raise MemoryError("oracle moments failed")
+        return rho, u, T
+
+    def forcing_moments(self):
+        Fv = np.zeros((3,) + self.shape)
+        S = np.zeros((6,) + self.shape)
+        rc = _load().orc_forcing_moments(self.nx, self.ny, self.nz, self.tau, self.mode,
+                                         _p(self.T_field), _p(self.F), _p(self.b), _p(Fv), _p(S))
+        if rc != 0:
+            raise MemoryError("oracle forcing moments failed")
+        return Fv, S
+
+    def invariants(self):
+        out = np.zeros(5)
+        _load().orc_invariants(self.nx, self.ny, self.nz, _p(self.F), _p(self.b), _p(out))
+        return out
+
+    def step_sites(self, sites, F=None, b=None):
+        """One step evaluated only at flat site indices `sites` (of the given or held state)."""
+        F = self.F if F is None else _f64(F).reshape((19,) + self.shape)
+        b = self.b if b is None else _f64(b).reshape((6,) + self.shape)
+        sites = np.ascontiguousarray(sites, dtype=np.int64)
+        m = sites.size
+        Fo = np.zeros((m, 19))
+        bo = np.zeros((m, 6))
+        rc = _load().orc_step_sites(self.nx, self.ny, self.nz, self.tau, self.mode,
+                                    _p(self.T_field), _p(F), _p(b), m,
+                                    sites.ctypes.data_as(C.POINTER(C.c_long)), _p(Fo), _p(bo))
+        if rc != 0:
+            raise ValueError("oracle step_sites failed (%d)" % rc)
+        return Fo, bo
