@@ -1,0 +1,208 @@
+"""Benchmark of the fused collide-and-stream sweep on one MI355X.
+
+Timed workload (one "step" = one full pass of the sweep over the lattice): the 3-D compressible
+Taylor-Green vortex on a 256^3 periodic D3Q19 lattice, Mach 0.5, tau = 0.55, FP32 storage and
+arithmetic, inputs resident in HBM.  W untimed warm-up steps, then K steps between HIP events
+recorded on the lattice's stream (barrier + synchronize on both sides).
+
+Also reported on the same JSON line:
+  roofline      algorithmic bytes per step (2 x 25 values x 4 B per site) over the measured
+                average step duration, against the 8 TB/s HBM peak; `traffic` from the committed
+                rocprofv3 FETCH_SIZE / WRITE_SIZE counters when they match the current kernel
+                sources, else null;
+  variants      the 2000-step run in FP64, FP32, FP16- and BF16-deviation storage: MLUPS and the
+                relative L2 error of rho, u, T against the FP64-storage run, kinetic-energy decay;
+  cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded sample (a 48^3
+                Taylor-Green vortex for ~10 s).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline, FP32 vs FP16-storage at stated L2 err; served p99"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
+VALUES_PER_LUP = 2 * (19 + 6)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2501_00620_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, workload, launch_sites):
+    """HBM bytes per launch from committed PMC counters, if taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def timed_steps(lat, steps, warmup):
+    import torch
+    lat.step(warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    stream = lat.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3  # seconds
+
+
+def rel_l2(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def run_variants(n, steps, tau, mach, every=500):
+    """FP64 / FP32 / FP16dev / BF16dev storage over the full run; errors against FP64."""
+    import torch
+    from paper_2501_00620_amd import lbm, workloads
+    rho0, u0, T0 = workloads.taylor_green(n, mach=mach)
+    out = {}
+    ref = None
+    for storage in ("f64", "f32", "f16dev", "bf16dev"):
+        lat = lbm.Lattice(n, n, n, tau, storage=storage)
+        lat.set_fields(rho0, u0, T0)
+        ke = []
+        t_total = 0.0
+        done = 0
+        while done < steps:
+            k = min(every, steps - done)
+            t_total += timed_steps(lat, k, 0)
+            done += k
+            r, u, T = lat.moments()
+            ke.append(float((0.5 * r * (u * u).sum(0)).sum() / r.sum()))
+        r, u, T = lat.moments()
+        bad = lat.health()
+        rec = {"mlups": n ** 3 * steps / t_total / 1e6, "kinetic_energy": ke,
+               "nonfinite_sites": bad[0]}
+        if ref is None:
+            ref = (r, u, T)
+        else:
+            rec["rel_l2_vs_f64"] = {"rho": rel_l2(r, ref[0]), "u": rel_l2(u, ref[1]), "T": rel_l2(T, ref[2])}
+        out[storage] = rec
+        del lat
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(seconds=10.0, n=48, mach=0.5, tau=0.55):
+    import oracle
+    from paper_2501_00620_amd import workloads
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rho, u, T = workloads.taylor_green(n, mach=mach)
+    o = oracle.OracleLattice(n, n, n, tau)
+    o.init(rho, u, T)
+    o.step(1)
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < seconds:
+        o.step(2)
+        steps += 2
+    dt = time.perf_counter() - t0
+    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"Taylor-Green vortex {n}^3, Mach {mach}, tau {tau}, FP64, {steps} steps "
+                      f"({dt:.1f} s) on {threads} OpenMP threads"}
+
+
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--kernel", default="auto")
+    ap.add_argument("--variant-steps", type=int, default=2000)
+    ap.add_argument("--quick", action="store_true", help="skip the precision variants and the CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the sweep has no multi-GPU path in this build "
+              "(domain decomposition is design-only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    from paper_2501_00620_amd import lbm, workloads
+    n, tau, mach = args.n, 0.55, 0.5
+    rho, u, T = workloads.taylor_green(n, mach=mach)
+    lat = lbm.Lattice(n, n, n, tau, storage=args.storage, kernel=args.kernel)
+    lat.set_fields(rho, u, T)
+    torch.cuda.synchronize()
+    secs = timed_steps(lat, args.steps, args.warmup)
+    health = lat.health()
+    sites = n ** 3
+    ms_per_step = secs * 1e3 / args.steps
+    mlups = sites * args.steps / secs / 1e6
+    bytes_per_step = sites * VALUES_PER_LUP * BYTES_PER_VALUE[args.storage]
+    achieved = bytes_per_step / (secs / args.steps) / 1e9
+    kname = "k_fused" if args.kernel in ("auto", "fused") else "k_two_pass"
+    workload = f"tgv{n}_{args.storage}"
+    traffic = traffic_from_profiles(kname, workload, sites)
+    del lat
+    torch.cuda.empty_cache()
+
+    line = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.storage == "f32" else args.storage,
+        "data": "synthetic (seeded Taylor-Green vortex initial fields)",
+        "config": {"workload": f"3-D compressible Taylor-Green vortex {n}^3 periodic D3Q19, Mach {mach}, "
+                               f"tau {tau}, {args.storage} storage", "nx": n, "ny": n, "nz": n, "tau": tau,
+                   "mach": mach, "storage": args.storage, "mode": "thermal", "kernel": kname,
+                   "health_nonfinite_sites": health[0]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_per_step},
+    }
+    if not args.quick:
+        line["variants"] = run_variants(n, args.variant_steps, tau, mach)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,146 @@
+/*
+ * lbm.h -- C ABI of liblbm, the MI355X (gfx950) implementation of the bump-function D3Q19
+ * lattice Boltzmann step of Afrasiabian & Denniston, "A Novel Velocity Discretization for
+ * Lattice Boltzmann Method: Application to Compressible Flow" (arXiv:2501.00620).
+ *
+ * The operation behind every entry point is one time step of Sec. II C of the paper: the
+ * populations fbar_i and the variance bbar of the bump functions (Eqs. 49-50, 62-66) are
+ * relaxed by the single-relaxation-time update (Eq. 55) towards the equilibria of Appendix A,
+ * with the forcing of Eqs. 58-61 built from isotropic finite differences of rho*b and
+ * rho*u*b, and then streamed along the D3Q19 velocities with bbar carried by the arriving
+ * populations (Eq. 66).  Lattice units throughout: dx = dt = c = 1, periodic in x, y and z.
+ *
+ * Conventions shared by all calls
+ *  - Fields are structure of arrays, x fastest: a scalar field is nz*ny*nx values, C order
+ *    (z, y, x); a vector field is 3 such planes (x, y, z components); the population state is
+ *    19 planes in the paper's velocity order (rows 2-4 of Table I); bbar is 6 planes in the
+ *    order xx, yy, zz, xy, xz, yz.
+ *  - Pointers are plain addresses.  `on_device` = 1: device pointers on the lattice's GPU
+ *    (e.g. torch CUDA tensors' data_ptr()); 0: host pointers.
+ *  - Ownership: the library owns all lattice memory.  The caller owns every buffer it passes and
+ *    may reuse it once the call returns; calls that read or write caller buffers finish that
+ *    access (on the lattice's stream, synchronised) before returning.
+ *  - Streams: each lattice runs on the HIP stream given at creation (NULL = the null stream).
+ *    lbm_step is asynchronous on that stream; the other calls synchronise it before returning.
+ *  - Errors: every int-returning call returns LBM_OK (0) or a negative code below; a readable
+ *    message for the calling thread is available from lbm_last_error().  No C++ exception
+ *    crosses this interface.  Handles are not thread-safe; the server is internally locked.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_ERR_ARG (-1)      /* bad size, tau <= 0, rho <= 0, unknown enum, NULL pointer   */
+#define LBM_ERR_OOM (-2)      /* device allocation failed                                    */
+#define LBM_ERR_HIP (-3)      /* HIP runtime error; message carries the runtime's string     */
+#define LBM_ERR_DIVERGED (-4) /* non-finite value or rho <= 0 found by a health check        */
+#define LBM_ERR_RANGE (-5)    /* 16-bit deviation encode saturated (value clamped)          */
+#define LBM_ERR_BUSY (-6)     /* server: request queued, not admitted yet (not a failure)   */
+#define LBM_ERR_STATE (-7)    /* call out of order (e.g. step before set_fields)            */
+
+/* Storage precision of the populations and bbar in device memory.  F64 computes in double;
+ * the others compute in float.  F16DEV / BF16DEV store 16-bit deviations
+ * h = (value - ref) / scale from a reference equilibrium (ref_i = w_i rho_ref for the
+ * populations, (T_ref - 1/3) delta for bbar), with one power-of-two scale per stored field,
+ * fixed when the fields or the state are set. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2, LBM_BF16DEV = 3 } lbm_storage;
+
+/* Temperature closure.  THERMAL: T from the total second-moment trace of the bump expansion
+ * (Eq. 26), so mass, momentum and energy are conserved.  ISO: T is the prescribed per-site field
+ * given to lbm_set_fields (the paper's setting in all its experiments); mass and momentum are
+ * conserved. */
+typedef enum { LBM_THERMAL = 0, LBM_ISO = 1 } lbm_mode;
+
+/* Field dtypes accepted by set_fields / get_moments. */
+typedef enum { LBM_DTYPE_F64 = 0, LBM_DTYPE_F32 = 1 } lbm_dtype;
+
+typedef struct {
+    int nx, ny, nz;     /* lattice size, each >= 1; nx*ny*nz <= 2^31 - 1                   */
+    double tau;         /* relaxation time of Eq. 55 in units of dt; omega = 1/(tau + 1/2) */
+    double T_ref;       /* reference temperature of the deviation codec (usually 1/3)      */
+    double rho_ref;     /* reference density of the deviation codec (usually 1)            */
+    int storage;        /* lbm_storage                                                      */
+    int mode;           /* lbm_mode                                                         */
+} lbm_params;
+
+typedef struct lbm_lattice *lbm_handle;
+
+/* Allocate a lattice on the current HIP device.  `hip_stream` is a hipStream_t (may be NULL).
+ * Device memory: 2 x (19 + 6) values of the storage type per site, plus 9 compute-type values
+ * per site of gradient sources.  Errors: ARG, OOM, HIP. */
+int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out);
+
+/* Initialise from macroscopic fields (Sec. II B, Appendix A): fbar_i = feq_i(rho, u),
+ * bbar = beq(u, T) at every site.  rho: n values, u: 3n, T: n, all of `dtype`.  In ISO mode T
+ * is also kept as the prescribed temperature field.  For 16-bit storage the codec scales are
+ * chosen here from the initial deviations.  Errors: ARG (rho <= 0 or non-finite anywhere),
+ * RANGE, HIP. */
+int lbm_set_fields(lbm_handle h, const void *rho, const void *u, const void *T, int dtype,
+                   int on_device);
+
+/* Advance n_steps time steps (Sec. II C) on the lattice's stream; asynchronous.
+ * Errors: ARG (n_steps < 0), STATE (no fields set), HIP. */
+int lbm_step(lbm_handle h, long n_steps);
+
+/* Read the macroscopic moments of the current state: rho = sum fbar (Eq. 56), the corrected
+ * velocity of Eq. 57, and T (the corrected THERMAL temperature, or the prescribed ISO field).
+ * rho: n, u: 3n, T: n values of `dtype`.  Any pointer may be NULL to skip that field. */
+int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on_device);
+
+/* Checkpoint / parity: the post-stream state (fbar: 19n doubles, bbar: 6n doubles), decoded to
+ * double.  lbm_set_state loads such a state (re-encoding it; codec scales are re-chosen for
+ * 16-bit storage).  get then set then step is bit-identical to stepping on for F64 and F32. */
+int lbm_get_state(lbm_handle h, void *F, void *b, int on_device);
+int lbm_set_state(lbm_handle h, const void *F, const void *b, int on_device);
+
+/* Deviation codec (16-bit storage only): the 25 power-of-two scales and the 25 references
+ * (19 populations, then bbar xx yy zz xy xz yz) as doubles.  Decoding is ref + scale * h.
+ * Errors: ARG for F64/F32 storage or NULL pointers. */
+int lbm_get_codec(lbm_handle h, double *scales25, double *refs25);
+
+/* Raw stored 16-bit codes (16-bit storage only), right after lbm_set_state or lbm_set_fields
+ * (before any step): 19n codes of the populations and 6n codes of bbar, as uint16.
+ * Errors: ARG for F64/F32 storage, STATE after a step (bbar is then held in its pre-gather
+ * form). */
+int lbm_get_raw(lbm_handle h, void *F_codes, void *b_codes, int on_device);
+
+/* The stored representation, decoded to double: F = the post-stream populations (19n, as
+ * lbm_get_state) and b = bbar in the form it is held in (6n): gathered bbar(x) right after
+ * set_fields / set_state, otherwise the post-collision bbar*(x) of the last step, before it is
+ * carried along with the populations (Eq. 66).  *b_is_gathered reports which.  Exact for every
+ * storage (no re-association), so it is what a 16-bit path is checked on element by element. */
+int lbm_get_stored(lbm_handle h, void *F, void *b, int *b_is_gathered, int on_device);
+
+/* Global invariants in double precision (wavefront, block, then a fixed-order second pass, so
+ * the result is deterministic): out[0] mass, out[1..3] momentum sum fbar e, out[4] energy
+ * 1/2 sum (sum_i fbar_i |e_i|^2 + rho tr bbar). */
+int lbm_invariants(lbm_handle h, double out[5]);
+
+/* Health check: counts of sites with a non-finite stored value and with rho <= 0, and the
+ * largest |u*| (uncorrected velocity).  Returns LBM_ERR_DIVERGED if either count is nonzero. */
+int lbm_health(lbm_handle h, long counts[2], double *max_u);
+
+/* Per-step launch configuration. kernel: 0 = auto, 1 = two-pass (predictor sources to a
+ * buffer, then gradient + collision), 2 = fused z-marching sweep with LDS planes of sources. */
+int lbm_set_kernel(lbm_handle h, int kernel);
+
+/* Block until all work queued on the lattice's stream is done. */
+int lbm_sync(lbm_handle h);
+void lbm_destroy(lbm_handle h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+/* Steps taken since the last set_fields / set_state. */
+long lbm_steps_done(lbm_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -472,13 +472,15 @@ void orc_invariants(int nx, int ny, int nz, const double *F, const double *b, do
 }
 
 /* One step evaluated only at the listed sites of a full-size state, without stepping the rest:
- * Fout[19*m], bout[6*m] receive the post-stream state after one step at sites[m].  The output at
+ * Fout[19*m], bout[6*m] receive the post-stream state after one step at sites[m]; if bstar is
+ * not NULL, bstar[6*m] receives the post-collision bbar*(x) at the site itself (before it is
+ * carried along, i.e. the i = 0 upstream term).  The output at
  * x needs the collision at the 19 upstream sites x - e_i, and each of those needs the gradient
  * sources one hop further, so a 5x5x5 copy of the state centred on x (periodic wrap applied when
  * copying) holds everything; the same per-site functions as orc_step run on that copy, whose
  * own wrap-around is never read for the centre's result. */
 int orc_step_sites(int nx, int ny, int nz, double tau, int mode, const double *Tf, const double *F,
-                   const double *b, long nsites, const long *sites, double *Fout, double *bout)
+                   const double *b, long nsites, const long *sites, double *Fout, double *bout, double *bstar)
 {
     const long n = (long)nx * ny * nz;
     const int L = 5;
@@ -528,6 +530,8 @@ int orc_step_sites(int nx, int ny, int nz, double tau, int mode, const double *T
             Fout[m * Q + i] = Fo[i];
             rho += Fo[i];
             for (int k = 0; k < NB; k++) acc[k] += Fo[i] * bo[k];
+            if (i == 0 && bstar)
+                for (int k = 0; k < NB; k++) bstar[m * NB + k] = bo[k];
         }
         for (int k = 0; k < NB; k++) bout[m * NB + k] = acc[k] / rho;
     }

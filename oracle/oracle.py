@@ -41,7 +41,7 @@ def _load():
         _lib.orc_forcing_moments.argtypes = [i, i, i, d, i, P, P, P, P, P]
         _lib.orc_forcing_moments.restype = i
         _lib.orc_invariants.argtypes = [i, i, i, P, P, P]
-        _lib.orc_step_sites.argtypes = [i, i, i, d, i, P, P, P, l, C.POINTER(C.c_long), P, P]
+        _lib.orc_step_sites.argtypes = [i, i, i, d, i, P, P, P, l, C.POINTER(C.c_long), P, P, P]
         _lib.orc_step_sites.restype = i
     return _lib
 
@@ -168,17 +168,20 @@ class OracleLattice:
         _load().orc_invariants(self.nx, self.ny, self.nz, _p(self.F), _p(self.b), _p(out))
         return out
 
-    def step_sites(self, sites, F=None, b=None):
-        """One step evaluated only at flat site indices `sites` (of the given or held state)."""
+    def step_sites(self, sites, F=None, b=None, with_bstar=False):
+        """One step evaluated only at flat site indices `sites` (of the given or held state).
+        Returns (F, b) post-stream at the sites, plus bbar* (post-collision, before the gather)
+        at the sites if with_bstar."""
         F = self.F if F is None else _f64(F).reshape((19,) + self.shape)
         b = self.b if b is None else _f64(b).reshape((6,) + self.shape)
         sites = np.ascontiguousarray(sites, dtype=np.int64)
         m = sites.size
         Fo = np.zeros((m, 19))
         bo = np.zeros((m, 6))
+        bs = np.zeros((m, 6))
         rc = _load().orc_step_sites(self.nx, self.ny, self.nz, self.tau, self.mode,
                                     _p(self.T_field), _p(F), _p(b), m,
-                                    sites.ctypes.data_as(C.POINTER(C.c_long)), _p(Fo), _p(bo))
+                                    sites.ctypes.data_as(C.POINTER(C.c_long)), _p(Fo), _p(bo), _p(bs))
         if rc != 0:
             raise ValueError("oracle step_sites failed (%d)" % rc)
-        return Fo, bo
+        return (Fo, bo, bs) if with_bstar else (Fo, bo)

@@ -1,0 +1,641 @@
+// lbm_api.hip -- host side of the C ABI declared in include/lbm.h.
+//
+// One lattice = device buffers of the kernels in lbm_kernels.hpp plus a HIP stream.  Every
+// step of the method runs in those kernels; the host only validates arguments, chooses the
+// codec scales from device reductions, and enqueues launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/lbm.h"
+#include "lbm_fused.hpp"
+#include "lbm_kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t store_bytes(int storage) { return storage == LBM_F64 ? 8 : storage == LBM_F32 ? 4 : 2; }
+size_t compute_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
+
+}  // namespace
+
+struct lbm_lattice {
+    lbm_params p{};
+    hipStream_t stream = nullptr;
+    int n = 0;
+    void *F[2] = {nullptr, nullptr};
+    void *B[2] = {nullptr, nullptr};
+    void *src = nullptr;
+    void *Tf = nullptr;       // ISO temperature field (compute type), or null when uniform
+    double Tconst = 0.0;      // ISO uniform temperature, stored as theta = T - T_ref
+    int cur = 0;
+    bool gathered = true;
+    bool has_state = false;
+    long steps = 0;
+    Codec codec{};
+    double *partial = nullptr;  // 2 * RED_MAX_BLOCKS * RED_K (sum and max partials)
+    double *red_out = nullptr;  // RED_K
+    unsigned *flag = nullptr;   // saturation flag
+    int kernel = 0;
+};
+
+namespace {
+
+Geo geo(const lbm_lattice *h) { return Geo{h->p.nx, h->p.ny, h->p.nz, h->n}; }
+
+int blocks_for(int n) { return (n + BLOCK - 1) / BLOCK; }
+int red_blocks(int n) {
+    int b = blocks_for(n);
+    return b < RED_MAX_BLOCKS ? b : RED_MAX_BLOCKS;
+}
+
+template <typename C> StepConst<C> step_const(const lbm_lattice *h) {
+    StepConst<C> k;
+    const double omega = 1.0 / (h->p.tau + 0.5);
+    k.omega = (C)omega;
+    k.half_omega = (C)(0.5 * omega);
+    k.fcoef = (C)(1.0 - 0.5 * omega);
+    k.rho_ref = (C)h->p.rho_ref;
+    k.theta_ref = (C)(h->p.T_ref - 1.0 / 3.0);
+    k.K = (C)(h->p.rho_ref * (h->p.T_ref - 1.0 / 3.0));
+    k.iso = h->p.mode == LBM_ISO;
+    return k;
+}
+
+// Codec references: ref_i = w_i rho_ref, bbar_ref = (T_ref - 1/3) I; unit scales until chosen.
+void codec_defaults(lbm_lattice *h) {
+    const double w[Q] = {1.0 / 3, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                         1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                         1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    for (int i = 0; i < Q; i++) h->codec.ref[i] = w[i] * h->p.rho_ref;
+    for (int c = 0; c < NB; c++) h->codec.ref[Q + c] = c < 3 ? h->p.T_ref - 1.0 / 3.0 : 0.0;
+    for (int k = 0; k < NFIELD; k++) h->codec.scale[k] = h->codec.inv[k] = 1.0f;
+}
+
+// Power-of-two scale per field: the largest deviation maps to at most HMAX/16 (fp16), leaving
+// 16x headroom for growth before saturation.  A field that starts without deviation gets the
+// scale of a deviation of 1e-3 of its reference magnitude (1e-3 for bbar).
+void choose_scales(lbm_lattice *h, const double *absmax) {
+    if (h->p.storage != LBM_F16DEV) {
+        for (int k = 0; k < NFIELD; k++) h->codec.scale[k] = h->codec.inv[k] = 1.0f;
+        return;
+    }
+    const double target = 65504.0 / 16.0;
+    for (int k = 0; k < NFIELD; k++) {
+        double floor_dev = k < Q ? 1e-3 * std::fabs(h->codec.ref[k]) : 1e-3;
+        if (floor_dev <= 0) floor_dev = 1e-3;
+        const double m = absmax[k] > floor_dev ? absmax[k] : floor_dev;
+        const int e = (int)std::ceil(std::log2(m / target));
+        const double sc = std::ldexp(1.0, e);
+        h->codec.scale[k] = (float)sc;
+        h->codec.inv[k] = (float)(1.0 / sc);
+    }
+}
+
+template <typename Fn> int dispatch_storage(int storage, Fn &&fn) {
+    switch (storage) {
+    case LBM_F64: return fn(std::integral_constant<int, 0>{});
+    case LBM_F32: return fn(std::integral_constant<int, 1>{});
+    case LBM_F16DEV: return fn(std::integral_constant<int, 2>{});
+    case LBM_BF16DEV: return fn(std::integral_constant<int, 3>{});
+    }
+    return fail(LBM_ERR_ARG, "unknown storage %d", storage);
+}
+
+int check_launch() {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LBM_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+// Fold block partials into h->red_out[0..K) and copy to host.
+template <bool MAX> int finish_reduction(lbm_lattice *h, int nblocks, int K, double *host) {
+    hipLaunchKernelGGL(k_reduce_final<MAX>, dim3(1), dim3(BLOCK), 0, h->stream, h->partial, nblocks, K, h->red_out);
+    int rc = check_launch();
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(host, h->red_out, sizeof(double) * K, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int read_clear_flag(lbm_lattice *h, unsigned *val) {
+    HIP_TRY(hipMemcpyAsync(val, h->flag, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (*val) HIP_TRY(hipMemsetAsync(h->flag, 0, sizeof(unsigned), h->stream));
+    return LBM_OK;
+}
+
+// ---- one step ----------------------------------------------------------------------------------
+template <int S> int step_two_pass(lbm_lattice *h) {
+    using T = typename Storage<S>::T;
+    using C = typename Storage<S>::C;
+    const Geo g = geo(h);
+    const StepConst<C> k = step_const<C>(h);
+    const T *F = (const T *)h->F[h->cur];
+    const T *B = (const T *)h->B[h->cur];
+    T *Fo = (T *)h->F[1 - h->cur];
+    T *Bo = (T *)h->B[1 - h->cur];
+    C *src = (C *)h->src;
+    const C *Tf = (const C *)h->Tf;
+    const C Tc = (C)h->Tconst;
+    const dim3 grid(blocks_for(h->n)), block(BLOCK);
+    if (h->gathered) {
+        hipLaunchKernelGGL((k_predict<S, true>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k, h->codec);
+        hipLaunchKernelGGL((k_collide<S, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
+    } else {
+        hipLaunchKernelGGL((k_predict<S, false>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k, h->codec);
+        hipLaunchKernelGGL((k_collide<S, false>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
+    }
+    int rc = check_launch();
+    if (rc) return rc;
+    h->cur = 1 - h->cur;
+    h->gathered = false;
+    return LBM_OK;
+}
+
+template <int S> int step_fused(lbm_lattice *h) {
+    using T = typename Storage<S>::T;
+    using C = typename Storage<S>::C;
+    const Geo g = geo(h);
+    const StepConst<C> k = step_const<C>(h);
+    int rc = launch_fused<S>((const T *)h->F[h->cur], (const T *)h->B[h->cur], (T *)h->F[1 - h->cur],
+                             (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->flag,
+                             h->gathered, h->stream);
+    if (rc) return fail(LBM_ERR_HIP, "fused launch failed");
+    rc = check_launch();
+    if (rc) return rc;
+    h->cur = 1 - h->cur;
+    h->gathered = false;
+    return LBM_OK;
+}
+
+bool use_fused(const lbm_lattice *h) { return h->kernel != 1 && fused_supported(geo(h)); }
+
+}  // namespace
+
+// ===============================================================================================
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out) {
+    if (!p || !out) return fail(LBM_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_ERR_ARG, "lattice size must be >= 1");
+    const long long n = (long long)p->nx * p->ny * p->nz;
+    if (n > 2147483647LL) return fail(LBM_ERR_ARG, "lattice has more than 2^31-1 sites");
+    if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(LBM_ERR_ARG, "tau must be > 0");
+    if (p->storage < 0 || p->storage > 3) return fail(LBM_ERR_ARG, "unknown storage %d", p->storage);
+    if (p->mode != LBM_THERMAL && p->mode != LBM_ISO) return fail(LBM_ERR_ARG, "unknown mode %d", p->mode);
+    if (!(p->rho_ref > 0.0)) return fail(LBM_ERR_ARG, "rho_ref must be > 0");
+    lbm_lattice *h = new (std::nothrow) lbm_lattice();
+    if (!h) return fail(LBM_ERR_OOM, "host allocation failed");
+    h->p = *p;
+    h->n = (int)n;
+    h->stream = (hipStream_t)hip_stream;
+    const size_t sb = store_bytes(p->storage), cb = compute_bytes(p->storage);
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < 2 && e == hipSuccess; b++) {
+        e = hipMalloc(&h->F[b], sb * Q * (size_t)n);
+        if (e == hipSuccess) e = hipMalloc(&h->B[b], sb * NB * (size_t)n);
+    }
+    if (e == hipSuccess) e = hipMalloc(&h->src, cb * NSRC * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc((void **)&h->partial, sizeof(double) * 2 * RED_MAX_BLOCKS * RED_K);
+    if (e == hipSuccess) e = hipMalloc((void **)&h->red_out, sizeof(double) * RED_K);
+    if (e == hipSuccess) e = hipMalloc((void **)&h->flag, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(h->flag, 0, sizeof(unsigned));
+    if (e != hipSuccess) {
+        lbm_destroy(h);
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? LBM_ERR_OOM : LBM_ERR_HIP, "allocation: %s", hipGetErrorString(e));
+    }
+    codec_defaults(h);
+    *out = h;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_handle h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    for (int b = 0; b < 2; b++) {
+        if (h->F[b]) (void)hipFree(h->F[b]);
+        if (h->B[b]) (void)hipFree(h->B[b]);
+    }
+    if (h->src) (void)hipFree(h->src);
+    if (h->Tf) (void)hipFree(h->Tf);
+    if (h->partial) (void)hipFree(h->partial);
+    if (h->red_out) (void)hipFree(h->red_out);
+    if (h->flag) (void)hipFree(h->flag);
+    delete h;
+}
+
+int lbm_set_kernel(lbm_handle h, int kernel) {
+    if (!h || kernel < 0 || kernel > 2) return fail(LBM_ERR_ARG, "bad kernel choice");
+    if (kernel == 2 && !fused_supported(geo(h))) return fail(LBM_ERR_ARG, "fused sweep does not support this lattice shape");
+    h->kernel = kernel;
+    return LBM_OK;
+}
+
+long lbm_steps_done(lbm_handle h) { return h ? h->steps : -1; }
+
+int lbm_sync(lbm_handle h) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int lbm_set_fields(lbm_handle h, const void *rho, const void *u, const void *T, int dtype, int on_device) {
+    if (!h || !rho || !u || !T) return fail(LBM_ERR_ARG, "null argument");
+    if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_ARG, "unknown dtype %d", dtype);
+    const size_t n = h->n, eb = dtype == LBM_DTYPE_F64 ? 8 : 4;
+    // stage host inputs on the device
+    void *stage = nullptr;
+    const void *dr = rho, *du = u, *dT = T;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&stage, eb * 5 * n));
+        char *s = (char *)stage;
+        hipError_t e = hipMemcpyAsync(s, rho, eb * n, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(s + eb * n, u, eb * 3 * n, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(s + eb * 4 * n, T, eb * n, hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(stage);
+            return fail(LBM_ERR_HIP, "copy of fields: %s", hipGetErrorString(e));
+        }
+        dr = s;
+        du = s + eb * n;
+        dT = s + eb * 4 * n;
+    }
+    int rc = LBM_OK;
+    const Geo g = geo(h);
+    const int rb = red_blocks(h->n);
+    double absmax[NFIELD + 1];
+    codec_defaults(h);
+    if (dtype == LBM_DTYPE_F64)
+        hipLaunchKernelGGL(k_absmax_fields<double>, dim3(rb), dim3(BLOCK), 0, h->stream, (const double *)dr,
+                           (const double *)du, (const double *)dT, g, h->p.rho_ref, h->p.T_ref, h->partial);
+    else
+        hipLaunchKernelGGL(k_absmax_fields<float>, dim3(rb), dim3(BLOCK), 0, h->stream, (const float *)dr,
+                           (const float *)du, (const float *)dT, g, h->p.rho_ref, h->p.T_ref, h->partial);
+    rc = check_launch();
+    if (!rc) rc = finish_reduction<true>(h, rb, NFIELD + 1, absmax);
+    if (!rc && absmax[NFIELD] > 0) rc = fail(LBM_ERR_ARG, "fields contain rho <= 0 or non-finite values");
+    if (!rc) {
+        choose_scales(h, absmax);
+        // ISO: keep a per-site temperature field only if it is not uniform
+        if (h->Tf) {
+            (void)hipFree(h->Tf);
+            h->Tf = nullptr;
+        }
+        bool keepT = false;
+        if (h->p.mode == LBM_ISO) {
+            // uniform check on the host is cheap for host inputs; device inputs are kept as a field
+            if (!on_device) {
+                if (dtype == LBM_DTYPE_F64) {
+                    const double *t = (const double *)T;
+                    for (size_t i = 1; i < n && !keepT; i++) keepT = t[i] != t[0];
+                    h->Tconst = t[0] - h->p.T_ref;
+                } else {
+                    const float *t = (const float *)T;
+                    for (size_t i = 1; i < n && !keepT; i++) keepT = t[i] != t[0];
+                    h->Tconst = (double)t[0] - h->p.T_ref;
+                }
+            } else {
+                keepT = true;
+            }
+            if (keepT) {
+                hipError_t e = hipMalloc(&h->Tf, compute_bytes(h->p.storage) * n);
+                if (e != hipSuccess) rc = fail(LBM_ERR_OOM, "temperature field: %s", hipGetErrorString(e));
+            }
+        }
+    }
+    if (!rc) {
+        rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
+            constexpr int S = decltype(SI)::value;
+            using TT = typename Storage<S>::T;
+            using C = typename Storage<S>::C;
+            if (dtype == LBM_DTYPE_F64)
+                hipLaunchKernelGGL((k_init<S, double>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream,
+                                   (const double *)dr, (const double *)du, (const double *)dT, g, h->codec,
+                                   h->p.rho_ref, h->p.T_ref, (TT *)h->F[0], (TT *)h->B[0], (C *)h->Tf, h->flag);
+            else
+                hipLaunchKernelGGL((k_init<S, float>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream,
+                                   (const float *)dr, (const float *)du, (const float *)dT, g, h->codec,
+                                   h->p.rho_ref, h->p.T_ref, (TT *)h->F[0], (TT *)h->B[0], (C *)h->Tf, h->flag);
+            return check_launch();
+        });
+    }
+    unsigned sat = 0;
+    if (!rc) rc = read_clear_flag(h, &sat);
+    if (stage) (void)hipFree(stage);
+    if (rc) return rc;
+    h->cur = 0;
+    h->gathered = true;
+    h->has_state = true;
+    h->steps = 0;
+    if (sat) return fail(LBM_ERR_RANGE, "16-bit encode saturated during set_fields");
+    return LBM_OK;
+}
+
+int lbm_step(lbm_handle h, long n_steps) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (n_steps < 0) return fail(LBM_ERR_ARG, "n_steps < 0");
+    if (!h->has_state) return fail(LBM_ERR_STATE, "step before set_fields/set_state");
+    const bool fused = use_fused(h);
+    for (long i = 0; i < n_steps; i++) {
+        int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
+            constexpr int S = decltype(SI)::value;
+            return fused ? step_fused<S>(h) : step_two_pass<S>(h);
+        });
+        if (rc) return rc;
+        h->steps++;
+    }
+    return LBM_OK;
+}
+
+int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on_device) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (!h->has_state) return fail(LBM_ERR_STATE, "no state");
+    if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_ARG, "unknown dtype %d", dtype);
+    const size_t n = h->n, eb = dtype == LBM_DTYPE_F64 ? 8 : 4;
+    void *stage = nullptr;
+    char *dr = (char *)rho, *du = (char *)u, *dT = (char *)T;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&stage, eb * 5 * n));
+        dr = rho ? (char *)stage : nullptr;
+        du = u ? (char *)stage + eb * n : nullptr;
+        dT = T ? (char *)stage + eb * 4 * n : nullptr;
+    }
+    const Geo g = geo(h);
+    int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
+        constexpr int S = decltype(SI)::value;
+        using TT = typename Storage<S>::T;
+        using C = typename Storage<S>::C;
+        const StepConst<C> k = step_const<C>(h);
+        const TT *F = (const TT *)h->F[h->cur];
+        const TT *B = (const TT *)h->B[h->cur];
+        C *src = (C *)h->src;
+        const dim3 grid(blocks_for(h->n)), block(BLOCK);
+        auto launch = [&](auto GI, auto OI) {
+            constexpr bool G = decltype(GI)::value;
+            using OUT = typename decltype(OI)::type;
+            hipLaunchKernelGGL((k_predict<S, G>), grid, block, 0, h->stream, F, B, src, (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
+            hipLaunchKernelGGL((k_readout<S, G, OUT>), grid, block, 0, h->stream, F, B, (const C *)src, (const C *)h->Tf,
+                               (C)h->Tconst, g, k, h->codec, h->p.T_ref, (OUT *)dr, (OUT *)du, (OUT *)dT);
+        };
+        struct D { using type = double; };
+        struct Fl { using type = float; };
+        if (h->gathered) {
+            if (dtype == LBM_DTYPE_F64) launch(std::true_type{}, D{}); else launch(std::true_type{}, Fl{});
+        } else {
+            if (dtype == LBM_DTYPE_F64) launch(std::false_type{}, D{}); else launch(std::false_type{}, Fl{});
+        }
+        return check_launch();
+    });
+    if (!rc && !on_device) {
+        hipError_t e = hipSuccess;
+        if (rho) e = hipMemcpyAsync(rho, dr, eb * n, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && u) e = hipMemcpyAsync(u, du, eb * 3 * n, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && T) e = hipMemcpyAsync(T, dT, eb * n, hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "copy of moments: %s", hipGetErrorString(e));
+    }
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "moments: %s", hipGetErrorString(e));
+    }
+    if (stage) (void)hipFree(stage);
+    return rc;
+}
+
+int lbm_get_state(lbm_handle h, void *F, void *b, int on_device) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (!h->has_state) return fail(LBM_ERR_STATE, "no state");
+    const size_t n = h->n;
+    void *stage = nullptr;
+    double *dF = (double *)F, *dB = (double *)b;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&stage, sizeof(double) * NFIELD * n));
+        dF = F ? (double *)stage : nullptr;
+        dB = b ? (double *)stage + Q * n : nullptr;
+    }
+    const Geo g = geo(h);
+    int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
+        constexpr int S = decltype(SI)::value;
+        using TT = typename Storage<S>::T;
+        using C = typename Storage<S>::C;
+        const TT *Fs = (const TT *)h->F[h->cur];
+        const TT *Bs = (const TT *)h->B[h->cur];
+        if (h->gathered)
+            hipLaunchKernelGGL((k_decode_state<S, true>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream, Fs, Bs, g,
+                               h->codec, (C)h->p.rho_ref, dF, dB);
+        else
+            hipLaunchKernelGGL((k_decode_state<S, false>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream, Fs, Bs, g,
+                               h->codec, (C)h->p.rho_ref, dF, dB);
+        return check_launch();
+    });
+    if (!rc && !on_device) {
+        hipError_t e = hipSuccess;
+        if (F) e = hipMemcpyAsync(F, dF, sizeof(double) * Q * n, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && b) e = hipMemcpyAsync(b, dB, sizeof(double) * NB * n, hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "copy of state: %s", hipGetErrorString(e));
+    }
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "get_state: %s", hipGetErrorString(e));
+    }
+    if (stage) (void)hipFree(stage);
+    return rc;
+}
+
+int lbm_get_stored(lbm_handle h, void *F, void *b, int *b_is_gathered, int on_device) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (!h->has_state) return fail(LBM_ERR_STATE, "no state");
+    const size_t n = h->n;
+    void *stage = nullptr;
+    double *dF = (double *)F, *dB = (double *)b;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&stage, sizeof(double) * NFIELD * n));
+        dF = F ? (double *)stage : nullptr;
+        dB = b ? (double *)stage + Q * n : nullptr;
+    }
+    const Geo g = geo(h);
+    int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
+        constexpr int S = decltype(SI)::value;
+        using TT = typename Storage<S>::T;
+        hipLaunchKernelGGL((k_decode_stored<S>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream,
+                           (const TT *)h->F[h->cur], (const TT *)h->B[h->cur], g, h->codec, dF, dB);
+        return check_launch();
+    });
+    if (!rc && !on_device) {
+        hipError_t e = hipSuccess;
+        if (F) e = hipMemcpyAsync(F, dF, sizeof(double) * Q * n, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && b) e = hipMemcpyAsync(b, dB, sizeof(double) * NB * n, hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "copy of stored state: %s", hipGetErrorString(e));
+    }
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "get_stored: %s", hipGetErrorString(e));
+    }
+    if (stage) (void)hipFree(stage);
+    if (!rc && b_is_gathered) *b_is_gathered = h->gathered ? 1 : 0;
+    return rc;
+}
+
+int lbm_set_state(lbm_handle h, const void *F, const void *b, int on_device) {
+    if (!h || !F || !b) return fail(LBM_ERR_ARG, "null argument");
+    if (h->p.mode == LBM_ISO && !h->has_state)
+        return fail(LBM_ERR_STATE, "ISO mode: set_fields first (it provides the temperature field)");
+    const size_t n = h->n;
+    void *stage = nullptr;
+    const double *dF = (const double *)F, *dB = (const double *)b;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&stage, sizeof(double) * NFIELD * n));
+        hipError_t e = hipMemcpyAsync(stage, F, sizeof(double) * Q * n, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((double *)stage + Q * n, b, sizeof(double) * NB * n, hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(stage);
+            return fail(LBM_ERR_HIP, "copy of state: %s", hipGetErrorString(e));
+        }
+        dF = (const double *)stage;
+        dB = (const double *)stage + Q * n;
+    }
+    const Geo g = geo(h);
+    const int rb = red_blocks(h->n);
+    double absmax[NFIELD + 1];
+    codec_defaults(h);
+    hipLaunchKernelGGL(k_absmax_state, dim3(rb), dim3(BLOCK), 0, h->stream, dF, dB, g, h->codec, h->partial);
+    int rc = check_launch();
+    if (!rc) rc = finish_reduction<true>(h, rb, NFIELD + 1, absmax);
+    if (!rc && absmax[NFIELD] > 0) rc = fail(LBM_ERR_ARG, "state contains non-finite values");
+    if (!rc) {
+        choose_scales(h, absmax);
+        rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
+            constexpr int S = decltype(SI)::value;
+            using TT = typename Storage<S>::T;
+            hipLaunchKernelGGL((k_encode_state<S>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream, dF, dB, g,
+                               h->codec, (TT *)h->F[0], (TT *)h->B[0], h->flag);
+            return check_launch();
+        });
+    }
+    unsigned sat = 0;
+    if (!rc) rc = read_clear_flag(h, &sat);
+    if (stage) (void)hipFree(stage);
+    if (rc) return rc;
+    h->cur = 0;
+    h->gathered = true;
+    h->has_state = true;
+    h->steps = 0;
+    if (sat) return fail(LBM_ERR_RANGE, "16-bit encode saturated during set_state");
+    return LBM_OK;
+}
+
+int lbm_get_codec(lbm_handle h, double *scales25, double *refs25) {
+    if (!h || !scales25 || !refs25) return fail(LBM_ERR_ARG, "null argument");
+    if (h->p.storage != LBM_F16DEV && h->p.storage != LBM_BF16DEV) return fail(LBM_ERR_ARG, "not a 16-bit storage");
+    for (int k = 0; k < NFIELD; k++) {
+        scales25[k] = h->codec.scale[k];
+        refs25[k] = h->codec.ref[k];
+    }
+    return LBM_OK;
+}
+
+int lbm_get_raw(lbm_handle h, void *F_codes, void *b_codes, int on_device) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (h->p.storage != LBM_F16DEV && h->p.storage != LBM_BF16DEV) return fail(LBM_ERR_ARG, "not a 16-bit storage");
+    if (!h->has_state || !h->gathered || h->cur != 0) return fail(LBM_ERR_STATE, "raw codes only right after set_fields/set_state");
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (F_codes) HIP_TRY(hipMemcpyAsync(F_codes, h->F[0], 2 * Q * (size_t)h->n, kind, h->stream));
+    if (b_codes) HIP_TRY(hipMemcpyAsync(b_codes, h->B[0], 2 * NB * (size_t)h->n, kind, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int lbm_invariants(lbm_handle h, double out[5]) {
+    if (!h || !out) return fail(LBM_ERR_ARG, "null argument");
+    if (!h->has_state) return fail(LBM_ERR_STATE, "no state");
+    const Geo g = geo(h);
+    const int rb = red_blocks(h->n);
+    int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
+        constexpr int S = decltype(SI)::value;
+        using TT = typename Storage<S>::T;
+        using C = typename Storage<S>::C;
+        const TT *F = (const TT *)h->F[h->cur];
+        const TT *B = (const TT *)h->B[h->cur];
+        if (h->gathered)
+            hipLaunchKernelGGL((k_invariants<S, true>), dim3(rb), dim3(BLOCK), 0, h->stream, F, B, g, h->codec,
+                               (C)h->p.rho_ref, h->p.T_ref - 1.0 / 3.0, h->partial);
+        else
+            hipLaunchKernelGGL((k_invariants<S, false>), dim3(rb), dim3(BLOCK), 0, h->stream, F, B, g, h->codec,
+                               (C)h->p.rho_ref, h->p.T_ref - 1.0 / 3.0, h->partial);
+        return check_launch();
+    });
+    if (!rc) rc = finish_reduction<false>(h, rb, 5, out);
+    return rc;
+}
+
+int lbm_health(lbm_handle h, long counts[2], double *max_u) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (!h->has_state) return fail(LBM_ERR_STATE, "no state");
+    const Geo g = geo(h);
+    const int rb = red_blocks(h->n);
+    double *pmax = h->partial + (size_t)RED_MAX_BLOCKS * RED_K;
+    int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
+        constexpr int S = decltype(SI)::value;
+        using TT = typename Storage<S>::T;
+        using C = typename Storage<S>::C;
+        const TT *F = (const TT *)h->F[h->cur];
+        const TT *B = (const TT *)h->B[h->cur];
+        if (h->gathered)
+            hipLaunchKernelGGL((k_health<S, true>), dim3(rb), dim3(BLOCK), 0, h->stream, F, B, g, h->codec,
+                               (C)h->p.rho_ref, h->partial, pmax);
+        else
+            hipLaunchKernelGGL((k_health<S, false>), dim3(rb), dim3(BLOCK), 0, h->stream, F, B, g, h->codec,
+                               (C)h->p.rho_ref, h->partial, pmax);
+        return check_launch();
+    });
+    double sums[2] = {0, 0}, mx = 0;
+    if (!rc) rc = finish_reduction<false>(h, rb, 2, sums);
+    if (!rc) {
+        hipLaunchKernelGGL(k_reduce_final<true>, dim3(1), dim3(BLOCK), 0, h->stream, pmax, rb, 1, h->red_out);
+        rc = check_launch();
+        if (!rc) {
+            hipError_t e = hipMemcpyAsync(&mx, h->red_out, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "health: %s", hipGetErrorString(e));
+        }
+    }
+    if (rc) return rc;
+    if (counts) {
+        counts[0] = (long)sums[0];
+        counts[1] = (long)sums[1];
+    }
+    if (max_u) *max_u = mx;
+    if (sums[0] > 0 || sums[1] > 0) return fail(LBM_ERR_DIVERGED, "%ld non-finite sites, %ld sites with rho <= 0", (long)sums[0], (long)sums[1]);
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,388 @@
+// lbm_device.hpp -- per-site arithmetic of the bump-function D3Q19 step on gfx950.
+//
+// Method: Afrasiabian & Denniston, "A Novel Velocity Discretization for Lattice Boltzmann
+// Method: Application to Compressible Flow" (arXiv:2501.00620), Sec. II B-C and Appendix A.
+// Lattice units dx = dt = c = 1; c_s^2 = 1/3; omega = 1/(tau + 1/2) (Eq. 55).
+//
+// The forms used here are algebraic rearrangements chosen for few VALU operations:
+//  * feq (Appendix A) grouped per lattice direction class.  Rest:
+//      rho/9 (3 - 2|u|^2 - 6(ux^2 uy^2 + ux^2 uz^2 + uy^2 uz^2));
+//    face along axis a with sign s (o_a = |u|^2 - u_a^2):
+//      rho/18 (1 + 3 s u_a + 2 u_a^2 - 2 o_a + 6 u_a^2 o_a);
+//    edge in the (a,b) plane with q = s_a u_a + s_b u_b:
+//      rho/36 (1 - u_a^2 - u_b^2 - 6 u_a^2 u_b^2 + 3 q (1 + q)).
+//  * the forcing populations with the moments of Eqs. 58-61 in Hermite form,
+//      Phi_i = w_i [3 e_i.F + 9/2 (e_i.S.e_i - tr S / 3)],
+//    whose zeroth, first and second moments are 0, F and S on D3Q19.
+//  * the isotropic derivative d_a phi = 3 sum_i w_i e_ia phi(x + e_i) applied to the sources
+//    R = rho b and X_abg = rho u*_g b_ab as one sum over neighbours: with
+//    v_i = sum_a e_ia R_a. (x + e_i),  F = -3 sum_i w_i v_i  and
+//    S_bg = -3 sum_i w_i (v_ib u_g + v_ig u_b)(x + e_i).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int Q = 19;
+constexpr int NB = 6;     // bbar components xx yy zz xy xz yz
+constexpr int NSRC = 9;   // gradient sources per site: R (6) then u* (3)
+constexpr int NFIELD = Q + NB;
+
+// Velocity set and order of the paper (rows 2-4 of Table I).
+constexpr int EX[Q] = {0, 1, 0, -1, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0};
+constexpr int EY[Q] = {0, 0, 1, 0, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1};
+constexpr int EZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+// Weights w_i = feq_i(u = 0) / rho (Appendix A at rest): 1/3, 1/18 (faces), 1/36 (edges).
+constexpr double WQ[Q] = {1.0 / 3, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+// ------------------------------------------------------------------------------------------
+// Storage codecs.  S = 0: double, 1: float, 2: fp16, 3: bf16.  What is stored is always the
+// deviation of a field from its reference value (d_i or beta, see below); the 16-bit codes h
+// hold deviation / scale[k] (k = field: 0..18 populations, 19..24 b), so the deviation decodes
+// as scale[k] * h.  ref[k] is the reference value itself, added back only when the state is
+// read out in absolute terms.
+// ------------------------------------------------------------------------------------------
+struct Codec {
+    double ref[NFIELD];
+    float scale[NFIELD];
+    float inv[NFIELD];
+};
+
+template <int S> struct Storage;
+
+template <> struct Storage<0> {
+    using T = double;
+    using C = double;
+    static __device__ __forceinline__ C load(const T *p, size_t i, int, const Codec &) { return p[i]; }
+    static __device__ __forceinline__ void store(T *p, size_t i, int, C v, const Codec &, unsigned &) { p[i] = v; }
+};
+
+template <> struct Storage<1> {
+    using T = float;
+    using C = float;
+    static __device__ __forceinline__ C load(const T *p, size_t i, int, const Codec &) { return p[i]; }
+    static __device__ __forceinline__ void store(T *p, size_t i, int, C v, const Codec &, unsigned &) { p[i] = v; }
+};
+
+__device__ __forceinline__ float half_bits_to_float(uint16_t b) {
+    return (float)__builtin_bit_cast(_Float16, b);
+}
+// float -> fp16 code, round to nearest even; |h| > 65504 saturates and sets the flag, NaN is
+// kept (and flagged) so that a health check still sees it.
+__device__ __forceinline__ uint16_t float_to_half_bits(float h, unsigned &sat) {
+    if (h != h) {
+        sat = 1u;
+        return (uint16_t)0x7e00u;
+    }
+    if (!(fabsf(h) <= 65504.0f)) {
+        sat = 1u;
+        h = h > 0.0f ? 65504.0f : -65504.0f;
+    }
+    return __builtin_bit_cast(uint16_t, (_Float16)h);
+}
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+// float -> bf16 code, round to nearest even on the dropped 16 bits; NaN stays NaN.
+__device__ __forceinline__ uint16_t float_to_bf16_bits(float h, unsigned &sat) {
+    uint32_t u = __float_as_uint(h);
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+        sat = 1u;
+        return (uint16_t)0x7fc0u;
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);
+    if ((u & 0x7f800000u) == 0x7f800000u) sat = 1u;  // rounded to infinity
+    return (uint16_t)(u >> 16);
+}
+
+template <> struct Storage<2> {
+    using T = uint16_t;
+    using C = float;
+    static __device__ __forceinline__ C load(const T *p, size_t i, int k, const Codec &c) {
+        return c.scale[k] * half_bits_to_float(p[i]);
+    }
+    static __device__ __forceinline__ void store(T *p, size_t i, int k, C v, const Codec &c, unsigned &sat) {
+        p[i] = float_to_half_bits(v * c.inv[k], sat);
+    }
+};
+
+template <> struct Storage<3> {
+    using T = uint16_t;
+    using C = float;
+    static __device__ __forceinline__ C load(const T *p, size_t i, int k, const Codec &c) {
+        return c.scale[k] * bf16_bits_to_float(p[i]);
+    }
+    static __device__ __forceinline__ void store(T *p, size_t i, int k, C v, const Codec &c, unsigned &sat) {
+        p[i] = float_to_bf16_bits(v * c.inv[k], sat);
+    }
+};
+
+// ------------------------------------------------------------------------------------------
+// Per-site arithmetic (compute type C) in deviation variables.
+//
+// Every precision stores and computes deviations from the rest equilibrium at the reference
+// state (rho_ref, T_ref):  d_i = fbar_i - w_i rho_ref  and  beta = bbar - b_ref with
+// b_ref = (T_ref - 1/3) I  (beq at rest, Appendix A).  The macroscopic quantities then come
+// without cancellation:
+//    rho - rho_ref = sum d_i,   j = sum d_i e_i   (sum w_i e_i = 0),
+//    P := tr Pi - rho = sum d_i (|e_i|^2 - 1) = sum_edges d_i - d_0   (sum w_i |e_i|^2 = 1),
+//    theta := T - T_ref = (P + rho tr beta - rho |u|^2) / (3 rho)    (energy-conserving T),
+//    beq - b_ref = theta I + u u / 3,
+//    feq_i - w_i rho_ref = w_i (rho - rho_ref) + rho (feq_i(1, u) - w_i).
+// The isotropic derivative of rho*b is taken of R' = rho b - rho_ref b_ref (a constant
+// removed, same gradient); the second-moment source rho u b = u (R' + rho_ref b_ref) keeps it.
+// ------------------------------------------------------------------------------------------
+template <typename C> struct StepConst {
+    C omega;      // 1/(tau + 1/2)
+    C half_omega; // omega/2: b = bbar - (omega/2)(bbar - beq) (Eqs. 62-65)
+    C fcoef;      // 1 - omega/2 = tau/(tau + 1/2), the forcing weight of Eq. 55
+    C rho_ref;    // reference density of the deviation variables
+    C theta_ref;  // T_ref - 1/3, the diagonal of b_ref
+    C K;          // rho_ref * theta_ref
+    int iso;      // prescribed temperature (theta per site or constant)
+};
+
+// feq_i - w_i rho_ref (Appendix A, grouped form; see the header comment).
+template <typename C>
+__device__ __forceinline__ void equilibrium_dev(C drho, C rho, C ux, C uy, C uz, C f[Q]) {
+    const C x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
+    const C r9 = rho * C(1.0 / 9.0), r18 = rho * C(1.0 / 18.0), r36 = rho * C(1.0 / 36.0);
+    const C d3 = drho * C(1.0 / 3.0), d18 = drho * C(1.0 / 18.0), d36 = drho * C(1.0 / 36.0);
+    f[0] = d3 - r9 * (C(2) * (x2 + y2 + z2) + C(6) * (x2 * y2 + x2 * z2 + y2 * z2));
+    const C ox = y2 + z2, oy = x2 + z2, oz = x2 + y2;
+    const C ax = d18 + r18 * (C(2) * (x2 - ox) + C(6) * x2 * ox);
+    const C ay = d18 + r18 * (C(2) * (y2 - oy) + C(6) * y2 * oy);
+    const C az = d18 + r18 * (C(2) * (z2 - oz) + C(6) * z2 * oz);
+    const C tx = r18 * C(3) * ux, ty = r18 * C(3) * uy, tz = r18 * C(3) * uz;
+    f[1] = ax + tx;
+    f[3] = ax - tx;
+    f[2] = ay + ty;
+    f[4] = ay - ty;
+    f[5] = az + tz;
+    f[6] = az - tz;
+    const C bxy = d36 - r36 * (oz + C(6) * x2 * y2);
+    const C bxz = d36 - r36 * (oy + C(6) * x2 * z2);
+    const C byz = d36 - r36 * (ox + C(6) * y2 * z2);
+    const C r12 = rho * C(1.0 / 12.0);  // 3 rho / 36
+    C q;
+    q = ux + uy;  f[7] = bxy + r12 * q * (C(1) + q);
+    q = -q;       f[10] = bxy + r12 * q * (C(1) + q);
+    q = ux - uy;  f[8] = bxy + r12 * q * (C(1) + q);
+    q = -q;       f[9] = bxy + r12 * q * (C(1) + q);
+    q = ux + uz;  f[11] = bxz + r12 * q * (C(1) + q);
+    q = -q;       f[14] = bxz + r12 * q * (C(1) + q);
+    q = ux - uz;  f[12] = bxz + r12 * q * (C(1) + q);
+    q = -q;       f[13] = bxz + r12 * q * (C(1) + q);
+    q = uy + uz;  f[15] = byz + r12 * q * (C(1) + q);
+    q = -q;       f[18] = byz + r12 * q * (C(1) + q);
+    q = uy - uz;  f[16] = byz + r12 * q * (C(1) + q);
+    q = -q;       f[17] = byz + r12 * q * (C(1) + q);
+}
+
+// beq - b_ref = theta I + u u / 3 (Appendix A / Eq. 36 with P = rho T I).
+template <typename C>
+__device__ __forceinline__ void variance_eq_dev(C ux, C uy, C uz, C theta, C b[NB]) {
+    const C third = C(1.0 / 3.0);
+    b[0] = fma(ux * ux, third, theta);
+    b[1] = fma(uy * uy, third, theta);
+    b[2] = fma(uz * uz, third, theta);
+    b[3] = ux * uy * third;
+    b[4] = ux * uz * third;
+    b[5] = uy * uz * third;
+}
+
+// Moments of the deviation populations.
+template <typename C> struct PopMoments {
+    C drho, rho, jx, jy, jz, P;
+};
+template <typename C>
+__device__ __forceinline__ PopMoments<C> pop_moments(const C d[Q], C rho_ref) {
+    PopMoments<C> m;
+    const C faces = ((d[1] + d[3]) + (d[2] + d[4])) + (d[5] + d[6]);
+    const C edges = (((d[7] + d[8]) + (d[9] + d[10])) + ((d[11] + d[12]) + (d[13] + d[14]))) +
+                    ((d[15] + d[16]) + (d[17] + d[18]));
+    m.drho = (d[0] + faces) + edges;
+    m.rho = rho_ref + m.drho;
+    m.P = edges - d[0];
+    m.jx = ((d[1] - d[3]) + (d[7] + d[8]) - (d[9] + d[10])) + ((d[11] + d[12]) - (d[13] + d[14]));
+    m.jy = ((d[2] - d[4]) + (d[7] - d[8]) + (d[9] - d[10])) + ((d[15] + d[16]) - (d[17] + d[18]));
+    m.jz = ((d[5] - d[6]) + (d[11] - d[12]) + (d[13] - d[14])) + ((d[15] - d[16]) + (d[17] - d[18]));
+    return m;
+}
+
+// Step 1: predictor velocity and temperature, and the gradient sources R' and u*.
+// b = bbar - (omega/2)(bbar - beq(u*, T*)) is the physical variance of Eqs. 62-65 with the
+// uncorrected velocity inside beq, as the paper allows after Eq. 68.
+template <typename C>
+__device__ __forceinline__ void predictor_sources(const PopMoments<C> &m, const C beta[NB], C theta_iso,
+                                                  const StepConst<C> &k, C src[NSRC]) {
+    const C inv = C(1) / m.rho;
+    const C ux = m.jx * inv, uy = m.jy * inv, uz = m.jz * inv;
+    const C u2 = ux * ux + uy * uy + uz * uz;
+    const C trb = beta[0] + beta[1] + beta[2];
+    const C theta = k.iso ? theta_iso : (m.P + m.rho * (trb - u2)) * inv * C(1.0 / 3.0);
+    C beq[NB];
+    variance_eq_dev(ux, uy, uz, theta, beq);
+    C bp[NB];
+#pragma unroll
+    for (int c = 0; c < NB; c++) bp[c] = beta[c] - k.half_omega * (beta[c] - beq[c]);
+    const C dK = m.drho * k.theta_ref;  // (rho - rho_ref) theta_ref on the diagonal
+#pragma unroll
+    for (int c = 0; c < 3; c++) src[c] = fma(m.rho, bp[c], dK);
+#pragma unroll
+    for (int c = 3; c < NB; c++) src[c] = m.rho * bp[c];
+    src[6] = ux;
+    src[7] = uy;
+    src[8] = uz;
+}
+
+// Accumulates the isotropic-gradient forcing moments over the 18 neighbours.
+template <typename C> struct GradAcc {
+    C fF[3], fS[6];  // face sums (weight 1/18)
+    C eF[3], eS[6];  // edge sums (weight 1/36)
+};
+
+template <typename C, int I>
+__device__ __forceinline__ void grad_add(GradAcc<C> &g, const C s[NSRC], C K) {
+    // v = sum_a e_ia R'_a.   R' rows: x = (xx, xy, xz), y = (xy, yy, yz), z = (xz, yz, zz);
+    // the second-moment source uses the full R = R' + K I, i.e. v + K e_i.
+    constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
+    const C vx = C(ex) * s[0] + C(ey) * s[3] + C(ez) * s[4];
+    const C vy = C(ex) * s[3] + C(ey) * s[1] + C(ez) * s[5];
+    const C vz = C(ex) * s[4] + C(ey) * s[5] + C(ez) * s[2];
+    const C wx = vx + C(ex) * K, wy = vy + C(ey) * K, wz = vz + C(ez) * K;
+    const C ux = s[6], uy = s[7], uz = s[8];
+    constexpr bool face = (ex * ex + ey * ey + ez * ez) == 1;
+    C *F = face ? g.fF : g.eF;
+    C *S = face ? g.fS : g.eS;
+    F[0] += vx;
+    F[1] += vy;
+    F[2] += vz;
+    S[0] += C(2) * wx * ux;
+    S[1] += C(2) * wy * uy;
+    S[2] += C(2) * wz * uz;
+    S[3] += wx * uy + wy * ux;
+    S[4] += wx * uz + wz * ux;
+    S[5] += wy * uz + wz * uy;
+}
+
+template <typename C>
+__device__ __forceinline__ void grad_init(GradAcc<C> &g) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) g.fF[c] = g.eF[c] = C(0);
+#pragma unroll
+    for (int c = 0; c < 6; c++) g.fS[c] = g.eS[c] = C(0);
+}
+
+// F = -3 (face/18 + edge/36) = -(face/6 + edge/12), likewise S.
+template <typename C>
+__device__ __forceinline__ void grad_finish(const GradAcc<C> &g, C F[3], C S[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) F[c] = -(g.fF[c] * C(1.0 / 6.0) + g.eF[c] * C(1.0 / 12.0));
+#pragma unroll
+    for (int c = 0; c < 6; c++) S[c] = -(g.fS[c] * C(1.0 / 6.0) + g.eS[c] * C(1.0 / 12.0));
+}
+
+// Steps 3-5: corrected moments, equilibria, forcing and the BGK update, in place on the
+// deviations d and beta.  Returns the corrected u and theta = T - T_ref if asked.
+template <typename C>
+__device__ __forceinline__ void collide(C d[Q], C beta[NB], const PopMoments<C> &m, const C F[3],
+                                        const C S[6], C theta_iso, const StepConst<C> &k, C *out_u = nullptr,
+                                        C *out_theta = nullptr) {
+    const C inv = C(1) / m.rho;
+    const C ux = (m.jx + C(0.5) * F[0]) * inv;  // Eq. 57
+    const C uy = (m.jy + C(0.5) * F[1]) * inv;
+    const C uz = (m.jz + C(0.5) * F[2]) * inv;
+    const C trS = S[0] + S[1] + S[2];
+    C theta;
+    if (k.iso) {
+        theta = theta_iso;
+    } else {
+        const C trb = beta[0] + beta[1] + beta[2];
+        const C u2 = ux * ux + uy * uy + uz * uz;
+        theta = (m.P + C(0.5) * trS + m.rho * (trb - u2)) * inv * C(1.0 / 3.0);
+    }
+    if (out_u) {
+        out_u[0] = ux;
+        out_u[1] = uy;
+        out_u[2] = uz;
+    }
+    if (out_theta) *out_theta = theta;
+
+    C feq[Q];
+    equilibrium_dev(m.drho, m.rho, ux, uy, uz, feq);
+    C beq[NB];
+    variance_eq_dev(ux, uy, uz, theta, beq);
+#pragma unroll
+    for (int c = 0; c < NB; c++) beta[c] += k.omega * (beq[c] - beta[c]);
+
+    // forcing populations, Hermite form; g = fcoef * Phi
+    const C t3 = trS * C(1.0 / 3.0);
+    const C a18 = k.fcoef * C(1.0 / 18.0), a36 = k.fcoef * C(1.0 / 36.0);
+    const C hx = C(4.5) * (S[0] - t3), hy = C(4.5) * (S[1] - t3), hz = C(4.5) * (S[2] - t3);
+    const C Fx3 = C(3) * F[0], Fy3 = C(3) * F[1], Fz3 = C(3) * F[2];
+    C g[Q];
+    g[0] = k.fcoef * C(-0.5) * trS;
+    g[1] = a18 * (hx + Fx3);
+    g[3] = a18 * (hx - Fx3);
+    g[2] = a18 * (hy + Fy3);
+    g[4] = a18 * (hy - Fy3);
+    g[5] = a18 * (hz + Fz3);
+    g[6] = a18 * (hz - Fz3);
+    const C exy = C(4.5) * (S[0] + S[1] - t3), sxy = C(9) * S[3];
+    const C exz = C(4.5) * (S[0] + S[2] - t3), sxz = C(9) * S[4];
+    const C eyz = C(4.5) * (S[1] + S[2] - t3), syz = C(9) * S[5];
+    g[7] = a36 * (exy + sxy + (Fx3 + Fy3));
+    g[10] = a36 * (exy + sxy - (Fx3 + Fy3));
+    g[8] = a36 * (exy - sxy + (Fx3 - Fy3));
+    g[9] = a36 * (exy - sxy - (Fx3 - Fy3));
+    g[11] = a36 * (exz + sxz + (Fx3 + Fz3));
+    g[14] = a36 * (exz + sxz - (Fx3 + Fz3));
+    g[12] = a36 * (exz - sxz + (Fx3 - Fz3));
+    g[13] = a36 * (exz - sxz - (Fx3 - Fz3));
+    g[15] = a36 * (eyz + syz + (Fy3 + Fz3));
+    g[18] = a36 * (eyz + syz - (Fy3 + Fz3));
+    g[16] = a36 * (eyz - syz + (Fy3 - Fz3));
+    g[17] = a36 * (eyz - syz - (Fy3 - Fz3));
+#pragma unroll
+    for (int i = 0; i < Q; i++) d[i] += k.omega * (feq[i] - d[i]) + g[i];
+}
+
+// Periodic neighbour offsets of a site: X/Y/Z[d+1] hold the x index, the row offset and the
+// plane offset of coordinate (c + d) mod n for d = -1, 0, 1 (valid for any n >= 1).
+struct Nbr {
+    int X[3];
+    int Y[3];
+    int Z[3];
+    __device__ __forceinline__ int at(int dx, int dy, int dz) const { return Z[dz + 1] + Y[dy + 1] + X[dx + 1]; }
+};
+
+__device__ __forceinline__ Nbr make_nbr(int x, int y, int z, int nx, int ny, int nz) {
+    Nbr o;
+    const int nxy = nx * ny;
+    o.X[0] = x == 0 ? nx - 1 : x - 1;
+    o.X[1] = x;
+    o.X[2] = x == nx - 1 ? 0 : x + 1;
+    o.Y[0] = (y == 0 ? ny - 1 : y - 1) * nx;
+    o.Y[1] = y * nx;
+    o.Y[2] = (y == ny - 1 ? 0 : y + 1) * nx;
+    o.Z[0] = (z == 0 ? nz - 1 : z - 1) * nxy;
+    o.Z[1] = z * nxy;
+    o.Z[2] = (z == nz - 1 ? 0 : z + 1) * nxy;
+    return o;
+}
+
+// compile-time loop helper
+template <int I, int N> struct Unroll {
+    template <typename Fn> static __device__ __forceinline__ void run(Fn &&fn) {
+        fn(std::integral_constant<int, I>{});
+        Unroll<I + 1, N>::run(fn);
+    }
+};
+template <int N> struct Unroll<N, N> {
+    template <typename Fn> static __device__ __forceinline__ void run(Fn &&) {}
+};
+
+}  // namespace lbm

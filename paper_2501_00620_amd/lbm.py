@@ -1,0 +1,237 @@
+"""Python binding of liblbm (ctypes): argument marshalling only.
+
+Every step of the method runs in the HIP kernels behind the C ABI of ``include/lbm.h``; this
+module passes torch tensors' device pointers and the current torch stream to it.  There is no
+CPU fallback: if ``liblbm.so`` is missing or no HIP device is present, calls raise.
+
+Array shapes (x fastest):  rho, T (nz, ny, nx);  u (3, nz, ny, nx);
+state F (19, nz, ny, nx) and b (6, nz, ny, nx), float64.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK = 0
+ERRORS = {-1: "ARG", -2: "OOM", -3: "HIP", -4: "DIVERGED", -5: "RANGE", -6: "BUSY", -7: "STATE"}
+STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3}
+MODE = {"thermal": 0, "iso": 1}
+KERNEL = {"auto": 0, "two_pass": 1, "fused": 2}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblbm {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class lbm_params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("tau", C.c_double),
+                ("T_ref", C.c_double), ("rho_ref", C.c_double), ("storage", C.c_int), ("mode", C.c_int)]
+
+
+_lib = None
+
+# every symbol declared in include/lbm.h, with its ctypes signature
+SIGNATURES = {
+    "lbm_create": ([C.POINTER(lbm_params), C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "lbm_set_fields": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int], C.c_int),
+    "lbm_step": ([C.c_void_p, C.c_long], C.c_int),
+    "lbm_get_moments": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int], C.c_int),
+    "lbm_get_state": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
+    "lbm_set_state": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
+    "lbm_get_codec": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+    "lbm_get_raw": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
+    "lbm_get_stored": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.c_int], C.c_int),
+    "lbm_invariants": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
+    "lbm_health": ([C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_double)], C.c_int),
+    "lbm_set_kernel": ([C.c_void_p, C.c_int], C.c_int),
+    "lbm_sync": ([C.c_void_p], C.c_int),
+    "lbm_destroy": ([C.c_void_p], None),
+    "lbm_last_error": ([], C.c_char_p),
+    "lbm_steps_done": ([C.c_void_p], C.c_long),
+}
+
+
+def load_library(path=LIB_PATH):
+    """Load liblbm.so and declare its signatures; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built; run __graft_entry__.build() first")
+        lib = C.CDLL(path)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(rc):
+    if rc != LBM_OK:
+        raise LBMError(rc, _lib.lbm_last_error().decode())
+    return rc
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _device_tensor(a, dtype, shape):
+    """A contiguous CUDA tensor of `dtype` and `shape` holding `a` (numpy, CPU or CUDA tensor)."""
+    torch = _torch()
+    if isinstance(a, np.ndarray):
+        a = torch.from_numpy(np.ascontiguousarray(a))
+    if not torch.is_tensor(a):
+        a = torch.as_tensor(a)
+    a = a.to(device="cuda", dtype=dtype)
+    a = a.expand(shape) if tuple(a.shape) != tuple(shape) else a
+    return a.contiguous()
+
+
+class Lattice:
+    """A periodic nx*ny*nz bump-function D3Q19 lattice resident on the current HIP device."""
+
+    def __init__(self, nx, ny, nz, tau, storage="f32", mode="thermal", T_ref=1.0 / 3.0, rho_ref=1.0,
+                 stream=None, kernel="auto"):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a HIP device (torch.cuda.is_available() is False)")
+        lib = load_library()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.n = self.nx * self.ny * self.nz
+        self.storage, self.mode, self.tau = storage, mode, float(tau)
+        p = lbm_params(self.nx, self.ny, self.nz, float(tau), float(T_ref), float(rho_ref),
+                       STORAGE[storage], MODE[mode])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib.lbm_create(C.byref(p), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.set_kernel(kernel)
+
+    # -- lifetime ---------------------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_kernel(self, kernel):
+        _check(_lib.lbm_set_kernel(self._h, KERNEL[kernel] if isinstance(kernel, str) else int(kernel)))
+
+    # -- fields and state -------------------------------------------------------------------------
+    def _sync_torch(self):
+        # tensors handed to the library were written on torch's current stream
+        torch = _torch()
+        if torch.cuda.current_stream().cuda_stream != self.stream.cuda_stream:
+            torch.cuda.current_stream().synchronize()
+
+    def set_fields(self, rho, u, T, dtype=None):
+        torch = _torch()
+        dt = dtype or torch.float64
+        r = _device_tensor(rho, dt, self.shape)
+        uu = _device_tensor(u, dt, (3,) + self.shape)
+        t = _device_tensor(T, dt, self.shape)
+        self._sync_torch()
+        code = 0 if dt == torch.float64 else 1
+        _check(_lib.lbm_set_fields(self._h, C.c_void_p(r.data_ptr()), C.c_void_p(uu.data_ptr()),
+                                   C.c_void_p(t.data_ptr()), code, 1))
+
+    def step(self, n=1):
+        _check(_lib.lbm_step(self._h, int(n)))
+
+    def sync(self):
+        _check(_lib.lbm_sync(self._h))
+
+    def moments(self, dtype=None):
+        torch = _torch()
+        dt = dtype or torch.float64
+        rho = torch.empty(self.shape, dtype=dt, device="cuda")
+        u = torch.empty((3,) + self.shape, dtype=dt, device="cuda")
+        T = torch.empty(self.shape, dtype=dt, device="cuda")
+        self._sync_torch()
+        _check(_lib.lbm_get_moments(self._h, C.c_void_p(rho.data_ptr()), C.c_void_p(u.data_ptr()),
+                                    C.c_void_p(T.data_ptr()), 0 if dt == torch.float64 else 1, 1))
+        return rho, u, T
+
+    def get_state(self):
+        torch = _torch()
+        F = torch.empty((19,) + self.shape, dtype=torch.float64, device="cuda")
+        b = torch.empty((6,) + self.shape, dtype=torch.float64, device="cuda")
+        self._sync_torch()
+        _check(_lib.lbm_get_state(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(b.data_ptr()), 1))
+        return F, b
+
+    def get_stored(self):
+        """(F, b, b_is_gathered): the stored representation decoded to float64 (no gather)."""
+        torch = _torch()
+        F = torch.empty((19,) + self.shape, dtype=torch.float64, device="cuda")
+        b = torch.empty((6,) + self.shape, dtype=torch.float64, device="cuda")
+        g = C.c_int()
+        self._sync_torch()
+        _check(_lib.lbm_get_stored(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(b.data_ptr()), C.byref(g), 1))
+        return F, b, bool(g.value)
+
+    def set_state(self, F, b):
+        torch = _torch()
+        F = _device_tensor(F, torch.float64, (19,) + self.shape)
+        b = _device_tensor(b, torch.float64, (6,) + self.shape)
+        self._sync_torch()
+        _check(_lib.lbm_set_state(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(b.data_ptr()), 1))
+
+    def codec(self):
+        s = (C.c_double * 25)()
+        r = (C.c_double * 25)()
+        _check(_lib.lbm_get_codec(self._h, s, r))
+        return np.array(s[:]), np.array(r[:])
+
+    def raw_codes(self):
+        torch = _torch()
+        F = torch.empty((19,) + self.shape, dtype=torch.int16, device="cuda")
+        b = torch.empty((6,) + self.shape, dtype=torch.int16, device="cuda")
+        self._sync_torch()
+        _check(_lib.lbm_get_raw(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(b.data_ptr()), 1))
+        return F.cpu().numpy().view(np.uint16), b.cpu().numpy().view(np.uint16)
+
+    def invariants(self):
+        out = (C.c_double * 5)()
+        _check(_lib.lbm_invariants(self._h, out))
+        return np.array(out[:])
+
+    def health(self):
+        """(n_nonfinite, n_rho_nonpositive, max|u*|); raises LBMError DIVERGED if unhealthy."""
+        cnt = (C.c_long * 2)()
+        mx = C.c_double()
+        rc = _lib.lbm_health(self._h, cnt, C.byref(mx))
+        if rc not in (LBM_OK, -4):
+            _check(rc)
+        return int(cnt[0]), int(cnt[1]), float(mx.value)
+
+    @property
+    def steps_done(self):
+        return int(_lib.lbm_steps_done(self._h))
