@@ -81,6 +81,7 @@ template <typename C> StepConst<C> step_const(const lbm_lattice *h) {
     k.rho_ref = (C)h->p.rho_ref;
     k.theta_ref = (C)(h->p.T_ref - 1.0 / 3.0);
     k.K = (C)(h->p.rho_ref * (h->p.T_ref - 1.0 / 3.0));
+    k.om1 = (C)(1.0 - omega);
     k.iso = h->p.mode == LBM_ISO;
     return k;
 }

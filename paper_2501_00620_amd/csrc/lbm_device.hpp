@@ -141,6 +141,7 @@ template <typename C> struct StepConst {
     C rho_ref;    // reference density of the deviation variables
     C theta_ref;  // T_ref - 1/3, the diagonal of b_ref
     C K;          // rho_ref * theta_ref
+    C om1;        // 1 - omega
     int iso;      // prescribed temperature (theta per site or constant)
 };
 
@@ -244,7 +245,9 @@ template <typename C> struct GradAcc {
     C eF[3], eS[6];  // edge sums (weight 1/36)
 };
 
-template <typename C, int I>
+// The diagonal S sums collect v_b u_b once; grad_finish doubles them.  HASK: T_ref != 1/3, so
+// the second-moment source carries the constant rho_ref b_ref = K I as well.
+template <typename C, int I, bool HASK = true>
 __device__ __forceinline__ void grad_add(GradAcc<C> &g, const C s[NSRC], C K) {
     // v = sum_a e_ia R'_a.   R' rows: x = (xx, xy, xz), y = (xy, yy, yz), z = (xz, yz, zz);
     // the second-moment source uses the full R = R' + K I, i.e. v + K e_i.
@@ -252,7 +255,12 @@ __device__ __forceinline__ void grad_add(GradAcc<C> &g, const C s[NSRC], C K) {
     const C vx = C(ex) * s[0] + C(ey) * s[3] + C(ez) * s[4];
     const C vy = C(ex) * s[3] + C(ey) * s[1] + C(ez) * s[5];
     const C vz = C(ex) * s[4] + C(ey) * s[5] + C(ez) * s[2];
-    const C wx = vx + C(ex) * K, wy = vy + C(ey) * K, wz = vz + C(ez) * K;
+    C wx = vx, wy = vy, wz = vz;
+    if constexpr (HASK) {
+        wx = vx + C(ex) * K;
+        wy = vy + C(ey) * K;
+        wz = vz + C(ez) * K;
+    }
     const C ux = s[6], uy = s[7], uz = s[8];
     constexpr bool face = (ex * ex + ey * ey + ez * ez) == 1;
     C *F = face ? g.fF : g.eF;
@@ -260,12 +268,12 @@ __device__ __forceinline__ void grad_add(GradAcc<C> &g, const C s[NSRC], C K) {
     F[0] += vx;
     F[1] += vy;
     F[2] += vz;
-    S[0] += C(2) * wx * ux;
-    S[1] += C(2) * wy * uy;
-    S[2] += C(2) * wz * uz;
-    S[3] += wx * uy + wy * ux;
-    S[4] += wx * uz + wz * ux;
-    S[5] += wy * uz + wz * uy;
+    S[0] = fma(wx, ux, S[0]);
+    S[1] = fma(wy, uy, S[1]);
+    S[2] = fma(wz, uz, S[2]);
+    S[3] = fma(wx, uy, fma(wy, ux, S[3]));
+    S[4] = fma(wx, uz, fma(wz, ux, S[4]));
+    S[5] = fma(wy, uz, fma(wz, uy, S[5]));
 }
 
 template <typename C>
@@ -276,17 +284,31 @@ __device__ __forceinline__ void grad_init(GradAcc<C> &g) {
     for (int c = 0; c < 6; c++) g.fS[c] = g.eS[c] = C(0);
 }
 
-// F = -3 (face/18 + edge/36) = -(face/6 + edge/12), likewise S.
+// F = -3 (face/18 + edge/36) = -(face/6 + edge/12), likewise S (diagonal sums doubled).
 template <typename C>
 __device__ __forceinline__ void grad_finish(const GradAcc<C> &g, C F[3], C S[6]) {
 #pragma unroll
     for (int c = 0; c < 3; c++) F[c] = -(g.fF[c] * C(1.0 / 6.0) + g.eF[c] * C(1.0 / 12.0));
 #pragma unroll
-    for (int c = 0; c < 6; c++) S[c] = -(g.fS[c] * C(1.0 / 6.0) + g.eS[c] * C(1.0 / 12.0));
+    for (int c = 0; c < 3; c++) S[c] = -(g.fS[c] * C(1.0 / 3.0) + g.eS[c] * C(1.0 / 6.0));
+#pragma unroll
+    for (int c = 3; c < 6; c++) S[c] = -(g.fS[c] * C(1.0 / 6.0) + g.eS[c] * C(1.0 / 12.0));
 }
 
 // Steps 3-5: corrected moments, equilibria, forcing and the BGK update, in place on the
 // deviations d and beta.  Returns the corrected u and theta = T - T_ref if asked.
+//
+// Each population is updated as d' = (1 - omega) d + c with c = omega (feq - w rho_ref) + g,
+// g = (1 - omega/2) Phi.  Opposite velocities i, i' share the even part P and flip the sign of
+// the odd part M of c:  c_i = P + M,  c_i' = P - M.  Per pair (axis a, or plane (a,b) with
+// q = s_a u_a + s_b u_b):
+//   faces:  P = omega [drho/18 + rho/18 (2 u_a^2 - 2 o_a + 6 u_a^2 o_a)] + (fcoef/4)(S_aa - trS/3)
+//           M = omega rho u_a / 6 + (fcoef/6) F_a
+//   edges:  P = omega [drho/36 - rho/36 (u_a^2 + u_b^2 + 6 u_a^2 u_b^2) + rho q^2 / 12]
+//               + (fcoef/8)(S_aa + S_bb - trS/3) + s_a s_b (fcoef/4) S_ab
+//           M = omega rho q / 12 + (fcoef/12)(s_a F_a + s_b F_b)
+//   rest:   c = omega [drho/3 - rho/9 (2|u|^2 + 6(ux^2 uy^2 + ux^2 uz^2 + uy^2 uz^2))] - fcoef trS/2
+// (the grouped Appendix A equilibrium and the Hermite-form forcing written above).
 template <typename C>
 __device__ __forceinline__ void collide(C d[Q], C beta[NB], const PopMoments<C> &m, const C F[3],
                                         const C S[6], C theta_iso, const StepConst<C> &k, C *out_u = nullptr,
@@ -296,13 +318,13 @@ __device__ __forceinline__ void collide(C d[Q], C beta[NB], const PopMoments<C> 
     const C uy = (m.jy + C(0.5) * F[1]) * inv;
     const C uz = (m.jz + C(0.5) * F[2]) * inv;
     const C trS = S[0] + S[1] + S[2];
+    const C x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
     C theta;
     if (k.iso) {
         theta = theta_iso;
     } else {
         const C trb = beta[0] + beta[1] + beta[2];
-        const C u2 = ux * ux + uy * uy + uz * uz;
-        theta = (m.P + C(0.5) * trS + m.rho * (trb - u2)) * inv * C(1.0 / 3.0);
+        theta = (m.P + C(0.5) * trS + m.rho * (trb - (x2 + y2 + z2))) * inv * C(1.0 / 3.0);
     }
     if (out_u) {
         out_u[0] = ux;
@@ -311,43 +333,58 @@ __device__ __forceinline__ void collide(C d[Q], C beta[NB], const PopMoments<C> 
     }
     if (out_theta) *out_theta = theta;
 
-    C feq[Q];
-    equilibrium_dev(m.drho, m.rho, ux, uy, uz, feq);
-    C beq[NB];
-    variance_eq_dev(ux, uy, uz, theta, beq);
-#pragma unroll
-    for (int c = 0; c < NB; c++) beta[c] += k.omega * (beq[c] - beta[c]);
+    // beta <- beta + omega (beq - beta), beq - b_ref = theta I + u u / 3
+    const C third = C(1.0 / 3.0);
+    beta[0] = fma(k.omega, fma(x2, third, theta) - beta[0], beta[0]);
+    beta[1] = fma(k.omega, fma(y2, third, theta) - beta[1], beta[1]);
+    beta[2] = fma(k.omega, fma(z2, third, theta) - beta[2], beta[2]);
+    beta[3] = fma(k.omega, ux * uy * third - beta[3], beta[3]);
+    beta[4] = fma(k.omega, ux * uz * third - beta[4], beta[4]);
+    beta[5] = fma(k.omega, uy * uz * third - beta[5], beta[5]);
 
-    // forcing populations, Hermite form; g = fcoef * Phi
-    const C t3 = trS * C(1.0 / 3.0);
-    const C a18 = k.fcoef * C(1.0 / 18.0), a36 = k.fcoef * C(1.0 / 36.0);
-    const C hx = C(4.5) * (S[0] - t3), hy = C(4.5) * (S[1] - t3), hz = C(4.5) * (S[2] - t3);
-    const C Fx3 = C(3) * F[0], Fy3 = C(3) * F[1], Fz3 = C(3) * F[2];
-    C g[Q];
-    g[0] = k.fcoef * C(-0.5) * trS;
-    g[1] = a18 * (hx + Fx3);
-    g[3] = a18 * (hx - Fx3);
-    g[2] = a18 * (hy + Fy3);
-    g[4] = a18 * (hy - Fy3);
-    g[5] = a18 * (hz + Fz3);
-    g[6] = a18 * (hz - Fz3);
-    const C exy = C(4.5) * (S[0] + S[1] - t3), sxy = C(9) * S[3];
-    const C exz = C(4.5) * (S[0] + S[2] - t3), sxz = C(9) * S[4];
-    const C eyz = C(4.5) * (S[1] + S[2] - t3), syz = C(9) * S[5];
-    g[7] = a36 * (exy + sxy + (Fx3 + Fy3));
-    g[10] = a36 * (exy + sxy - (Fx3 + Fy3));
-    g[8] = a36 * (exy - sxy + (Fx3 - Fy3));
-    g[9] = a36 * (exy - sxy - (Fx3 - Fy3));
-    g[11] = a36 * (exz + sxz + (Fx3 + Fz3));
-    g[14] = a36 * (exz + sxz - (Fx3 + Fz3));
-    g[12] = a36 * (exz - sxz + (Fx3 - Fz3));
-    g[13] = a36 * (exz - sxz - (Fx3 - Fz3));
-    g[15] = a36 * (eyz + syz + (Fy3 + Fz3));
-    g[18] = a36 * (eyz + syz - (Fy3 + Fz3));
-    g[16] = a36 * (eyz - syz + (Fy3 - Fz3));
-    g[17] = a36 * (eyz - syz - (Fy3 - Fz3));
-#pragma unroll
-    for (int i = 0; i < Q; i++) d[i] += k.omega * (feq[i] - d[i]) + g[i];
+    const C om = k.omega, om1 = k.om1, fc = k.fcoef;
+    const C wr = om * m.rho, wd = om * m.drho;
+    const C wr9 = wr * C(1.0 / 9.0), wr18 = wr * C(1.0 / 18.0), wr36 = wr * C(1.0 / 36.0);
+    const C wr12 = wr * C(1.0 / 12.0), wr6 = wr * C(1.0 / 6.0);
+    const C wd18 = wd * C(1.0 / 18.0), wd36 = wd * C(1.0 / 36.0);
+    const C t3 = trS * third;
+    const C fc4 = fc * C(0.25), fc6 = fc * C(1.0 / 6.0), fc8 = fc * C(0.125), fc12 = fc * C(1.0 / 12.0);
+    const C xy = x2 * y2, xz = x2 * z2, yz = y2 * z2;
+    const C ox = y2 + z2, oy = x2 + z2, oz = x2 + y2;
+
+    // rest
+    d[0] = fma(om1, d[0], fma(wd, third, -wr9 * fma(C(2), x2 + ox, C(6) * (xy + xz + yz))) - fc * C(0.5) * trS);
+
+    // faces: pairs (1,3) x, (2,4) y, (5,6) z
+    auto face = [&](int ip, int im, C a2, C oa, C ua, C Saa, C Fa) {
+        const C P = fma(wr18, fma(C(2), a2 - oa, C(6) * a2 * oa), wd18) + fc4 * (Saa - t3);
+        const C M = fma(wr6, ua, fc6 * Fa);
+        d[ip] = fma(om1, d[ip], P + M);
+        d[im] = fma(om1, d[im], P - M);
+    };
+    face(1, 3, x2, ox, ux, S[0], F[0]);
+    face(2, 4, y2, oy, uy, S[1], F[1]);
+    face(5, 6, z2, oz, uz, S[2], F[2]);
+
+    // edges: in the (a,b) plane, pairs (+a+b, -a-b) and (+a-b, -a+b)
+    auto edges = [&](int ipp, int imm, int ipm, int imp, C a2b2, C a2b2x, C ua, C ub, C Saa, C Sbb, C Sab, C Fa,
+                     C Fb) {
+        const C base = fma(-wr36, fma(C(6), a2b2x, a2b2), wd36) + fc8 * (Saa + Sbb - t3);
+        const C sab = fc4 * Sab;
+        C q = ua + ub;
+        C P = fma(wr12, q * q, base) + sab;
+        C M = fma(wr12, q, fc12 * (Fa + Fb));
+        d[ipp] = fma(om1, d[ipp], P + M);
+        d[imm] = fma(om1, d[imm], P - M);
+        q = ua - ub;
+        P = fma(wr12, q * q, base) - sab;
+        M = fma(wr12, q, fc12 * (Fa - Fb));
+        d[ipm] = fma(om1, d[ipm], P + M);
+        d[imp] = fma(om1, d[imp], P - M);
+    };
+    edges(7, 10, 8, 9, oz, xy, ux, uy, S[0], S[1], S[3], F[0], F[1]);
+    edges(11, 14, 12, 13, oy, xz, ux, uz, S[0], S[2], S[4], F[0], F[2]);
+    edges(15, 18, 16, 17, ox, yz, uy, uz, S[1], S[2], S[5], F[1], F[2]);
 }
 
 // Periodic neighbour offsets of a site: X/Y/Z[d+1] hold the x index, the row offset and the

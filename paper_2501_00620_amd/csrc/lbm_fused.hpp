@@ -1,48 +1,133 @@
 // lbm_fused.hpp -- single-pass step: z-marching sweep with LDS planes of predictor sources.
 //
-// One work-group owns an xy tile of FTX x FTY sites and marches through a chunk of z planes.
+// One work-group owns an xy tile of TX x TY sites and marches through a chunk of z planes.
 // The forcing moments at a site need the predictor sources (rho b and u*, Eqs. 59-61 with
 // Eq. 68) of its 18 neighbours, and each source needs the site's post-stream populations and
-// its gathered bbar (Eq. 66), i.e. one more hop.  Per plane z the work-group
-//   A. evaluates the sources of plane z+1 on the tile plus a one-site ring (the ring overlaps
-//      the neighbouring tiles) into one of three LDS planes, keeping the tile's own
+// its gathered bbar (Eq. 66): bbar(y) = sum_i fbar_i(y) bbar*(y - e_i) / rho(y), one more hop.
+// Per plane z the work-group
+//   1. stages the post-collision bbar* of plane z+2 over the tile plus two rings in LDS
+//      (coalesced loads; each value is then read by up to 19 gathers from LDS);
+//   2. evaluates the sources of plane z+1 on the tile plus a one-site ring (the ring overlaps
+//      the neighbouring tiles) into one of three LDS source planes, keeping the tile's own
 //      populations, bbar and moments in registers for the next iteration;
-//   B. takes the isotropic gradients of plane z from the LDS planes z-1, z, z+1, collides the
-//      registers kept from the previous iteration, and pushes the results out.
-// Each site's state is read from HBM once per step for its own update (plus the ring, which
-// neighbouring tiles on the same XCD usually bring into L2 at about the same time) and written
-// once: 2 x 25 values per lattice update, the algorithmic minimum.
+//   3. takes the isotropic gradients of plane z from the source planes z-1, z, z+1, collides
+//      the registers kept from the previous iteration, and pushes the results out.
+// Each site's populations are read from HBM once per step for its own update (plus the ring,
+// which neighbouring tiles on the same XCD usually bring into L2 at about the same time) and
+// written once: 2 x 25 values per lattice update, the algorithmic minimum.
 //
 // Work-groups are numbered so that the ones dispatched to one XCD (block index mod 8) take
 // neighbouring tiles of the same z chunk, which share their rings through that XCD's L2.
 // Any lattice shape works: tile sites beyond the lattice are computed (wrapped) only as ring
-// sources and never stored; nz <= 2 evaluates each plane's sources once and reuses them.
+// sources and never stored; nz <= 2 stages and evaluates each plane once.
 #pragma once
 
 #include "lbm_kernels.hpp"
 
 namespace lbm {
 
-constexpr int FTX = 64, FTY = 4;
-constexpr int FNT = FTX * FTY;      // threads = tile sites
-constexpr int FHX = FTX + 2;        // LDS row length with the ring
-constexpr int FHY = FTY + 2;
-constexpr int FNS = FHX * FHY;      // source sites per LDS plane
-constexpr int FNH = FNS - FNT;      // ring sites
-
-#ifndef FUSED_WAVES_PER_EU
-#define FUSED_WAVES_PER_EU 2
+#ifndef GRAD_GROUP
+#define GRAD_GROUP 3    // neighbours per scheduling group in the gradient
 #endif
+#ifndef GATHER_GROUP
+#define GATHER_GROUP 5  // directions per scheduling group in the gather
+#endif
+
+template <int TY_> struct Tile {
+    static constexpr int TX = 64, TY = TY_;
+    static constexpr int NT = TX * TY;            // threads = tile sites
+    static constexpr int HX = TX + 2, HY = TY + 2;
+    static constexpr int NS = HX * HY;            // source sites per LDS plane (tile + ring)
+    static constexpr int NH = NS - NT;            // ring sites
+    static constexpr int BX = TX + 4, BY = TY + 4;
+    static constexpr int NB2 = BX * BY;           // bbar* staging sites (tile + two rings)
+};
+
+// 4- and 2-byte storage compute in float: 64 x 8 tiles (71 KB of sources + 59 KB of staged
+// bbar*); double needs twice the bytes, so 64 x 2.
+template <int S> struct TileFor { using type = Tile<8>; };
+template <> struct TileFor<0> { using type = Tile<2>; };
 
 struct FusedGeo {
     int tiles_x, tiles_y, nchunks, zchunk;
 };
 
+// Buffer addressing of an array of planes (n values each): one buffer resource (4 SGPRs) per
+// group of PPG planes, a 32-bit per-lane byte offset of the site, and the plane's byte offset
+// inside its group as the scalar offset.  No 64-bit per-lane address is ever formed, and a
+// group stays below 4 GiB for every lattice the fused kernel accepts.
+template <int S> struct Buf {
+    using T = typename Storage<S>::T;
+    using C = typename Storage<S>::C;
+    static constexpr int PPG = S == 0 ? 3 : (S == 1 ? 5 : 9);
+    static constexpr int NG = (Q + PPG - 1) / PPG;
+    __amdgpu_buffer_rsrc_t r[NG];
+    int pb;  // plane bytes
+
+    __device__ __forceinline__ void init(const T *base, int nplanes, int n) {
+        pb = n * (int)sizeof(T);
+#pragma unroll
+        for (int g = 0; g < NG; g++) {
+            const int np = nplanes - g * PPG;
+            if (np > 0) {
+                const unsigned bytes = (unsigned)(np < PPG ? np : PPG) * (unsigned)pb;
+                r[g] = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)g * PPG * n), (short)0, (int)bytes,
+                                                         0x00020000);
+            }
+        }
+    }
+    template <int K> __device__ __forceinline__ C load(int off, const Codec &cd) const {
+        constexpr int g = K / PPG, j = K % PPG;
+        const __amdgpu_buffer_rsrc_t rs = r[g];
+        if constexpr (S == 0) {
+            auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, j * pb, 0);
+            return __builtin_bit_cast(double, v);
+        } else if constexpr (S == 1) {
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, j * pb, 0));
+        } else if constexpr (S == 2) {
+            return cd.scale[K] * half_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, j * pb, 0));
+        } else {
+            return cd.scale[K] * bf16_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, j * pb, 0));
+        }
+    }
+    // plane K of this array holds codec field F0 + K
+    template <int K, int F0> __device__ __forceinline__ C loadf(int off, const Codec &cd) const {
+        constexpr int g = K / PPG, j = K % PPG;
+        const __amdgpu_buffer_rsrc_t rs = r[g];
+        if constexpr (S == 0) {
+            auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, j * pb, 0);
+            return __builtin_bit_cast(double, v);
+        } else if constexpr (S == 1) {
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, j * pb, 0));
+        } else if constexpr (S == 2) {
+            return cd.scale[F0 + K] * half_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, j * pb, 0));
+        } else {
+            return cd.scale[F0 + K] * bf16_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, j * pb, 0));
+        }
+    }
+    template <int K, int F0> __device__ __forceinline__ void storef(int off, C v, const Codec &cd, unsigned &sat) const {
+        constexpr int g = K / PPG, j = K % PPG;
+        const __amdgpu_buffer_rsrc_t rs = r[g];
+        if constexpr (S == 0) {
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0)), v),
+                                                  rs, off, j * pb, 0);
+        } else if constexpr (S == 1) {
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, j * pb, 0);
+        } else if constexpr (S == 2) {
+            __builtin_amdgcn_raw_buffer_store_b16(float_to_half_bits(v * cd.inv[F0 + K], sat), rs, off, j * pb, 0);
+        } else {
+            __builtin_amdgcn_raw_buffer_store_b16(float_to_bf16_bits(v * cd.inv[F0 + K], sat), rs, off, j * pb, 0);
+        }
+    }
+};
+
+// What a thread carries from the source evaluation of its site to the site's collision one
+// plane later: the gathered bbar (which cannot be re-gathered then, its upstream plane is no
+// longer staged) and the ISO temperature offset.  The populations are re-read at the collision
+// (the same work-group read them one plane earlier, so they come from L2).
 template <typename C> struct SiteState {
-    C d[Q];
     C beta[NB];
-    PopMoments<C> m;
-    C theta;  // prescribed temperature offset (ISO)
+    C theta;
 };
 
 __device__ __forceinline__ int wrapc(int v, int n) {
@@ -50,47 +135,104 @@ __device__ __forceinline__ int wrapc(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-// Sources of one site (global coordinates already wrapped) into an LDS plane; optionally keep
-// its state.
-template <int S, bool GATHERED, bool KEEP>
-__device__ __forceinline__ void source_site(const typename Storage<S>::T *__restrict__ F,
-                                            const typename Storage<S>::T *__restrict__ B,
-                                            const typename Storage<S>::C *__restrict__ Tf,
-                                            typename Storage<S>::C Tconst, const Geo &g,
-                                            const StepConst<typename Storage<S>::C> &k, const Codec &cd, int x,
-                                            int y, int z, typename Storage<S>::C *plane, int lidx,
-                                            SiteState<typename Storage<S>::C> &keep) {
+template <int S>
+__device__ __forceinline__ void load_pops(const Buf<S> &bF, int off, const Codec &cd, typename Storage<S>::C d[Q]) {
+    Unroll<0, Q>::run([&](auto I) { d[I] = bF.template loadf<I, 0>(off, cd); });
+}
+
+// Sources of one site from its stored, gathered bbar (the first step after the state was set).
+template <int S, int NS, bool KEEP>
+__device__ __forceinline__ void source_site_gathered(const Buf<S> &bF, const Buf<S> &bB,
+                                                     const typename Storage<S>::C *__restrict__ Tf,
+                                                     typename Storage<S>::C Tconst,
+                                                     const StepConst<typename Storage<S>::C> &k, const Codec &cd,
+                                                     int s, typename Storage<S>::C *plane, int lidx,
+                                                     SiteState<typename Storage<S>::C> &keep) {
     using C = typename Storage<S>::C;
-    const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
-    const int s = nb.at(0, 0, 0);
+    const int off = s * (int)sizeof(typename Storage<S>::T);
     C d[Q], beta[NB];
-    PopMoments<C> m;
-    load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, d, beta, m);
+    load_pops<S>(bF, off, cd, d);
+    const PopMoments<C> m = pop_moments(d, k.rho_ref);
+    Unroll<0, NB>::run([&](auto c) { beta[c] = bB.template loadf<c, Q>(off, cd); });
     const C th = site_T(Tf, Tconst, s);
     C o[NSRC];
     predictor_sources(m, beta, th, k, o);
 #pragma unroll
-    for (int c = 0; c < NSRC; c++) plane[c * FNS + lidx] = o[c];
+    for (int c = 0; c < NSRC; c++) plane[c * NS + lidx] = o[c];
     if constexpr (KEEP) {
 #pragma unroll
-        for (int i = 0; i < Q; i++) keep.d[i] = d[i];
-#pragma unroll
         for (int c = 0; c < NB; c++) keep.beta[c] = beta[c];
-        keep.m = m;
         keep.theta = th;
     }
 }
 
-// Occupancy: two waves per SIMD (two 256-thread work-groups per CU) leave 256 VGPRs per lane for
-// the two planes of site state and the gradient sums; three would cap it at 168 and spill.
-template <int S, bool GATHERED>
-__global__ void __launch_bounds__(FNT) __attribute__((amdgpu_waves_per_eu(FUSED_WAVES_PER_EU)))
+// Sources of one site whose bbar* neighbourhood is staged in LDS: the gather of Eq. 66 reads
+// the staged planes bs[0..2] (planes z-1, z, z+1); bidx is the site's staging index.
+template <int S, typename TL, bool KEEP>
+__device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typename Storage<S>::C *__restrict__ Tf,
+                                                   typename Storage<S>::C Tconst,
+                                                   const StepConst<typename Storage<S>::C> &k, const Codec &cd,
+                                                   int s, int bidx, const typename Storage<S>::C *const bs[3],
+                                                   typename Storage<S>::C *plane, int lidx,
+                                                   SiteState<typename Storage<S>::C> &keep) {
+    using C = typename Storage<S>::C;
+    C d[Q], beta[NB];
+    load_pops<S>(bF, s * (int)sizeof(typename Storage<S>::T), cd, d);
+    const PopMoments<C> m = pop_moments(d, k.rho_ref);
+    C acc[NB];
+#pragma unroll
+    for (int c = 0; c < NB; c++) acc[c] = C(0);
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
+        const C *pl = bs[1 - ez] + bidx;  // upstream site y - e_i lies in plane z - e_iz
+        constexpr int off = -ey * TL::BX - ex;
+        const C wgt = fma(C(WQ[I]), k.rho_ref, d[I]);
+#pragma unroll
+        for (int c = 0; c < NB; c++) acc[c] = fma(wgt, pl[c * TL::NB2 + off], acc[c]);
+        if constexpr (I % GATHER_GROUP == GATHER_GROUP - 1) __builtin_amdgcn_sched_barrier(0);
+    });
+    const C inv = C(1) / m.rho;
+#pragma unroll
+    for (int c = 0; c < NB; c++) beta[c] = acc[c] * inv;
+    const C th = site_T(Tf, Tconst, s);
+    C o[NSRC];
+    predictor_sources(m, beta, th, k, o);
+#pragma unroll
+    for (int c = 0; c < NSRC; c++) plane[c * TL::NS + lidx] = o[c];
+    if constexpr (KEEP) {
+#pragma unroll
+        for (int c = 0; c < NB; c++) keep.beta[c] = beta[c];
+        keep.theta = th;
+    }
+}
+
+#ifndef FUSED_WAVES_PER_EU
+#define FUSED_WAVES_PER_EU 2
+#endif
+
+// Occupancy: the LDS (about 130 KB of 160 KB for float) admits one 512-thread work-group per
+// CU, i.e. two waves per SIMD.  HASK: T_ref != 1/3 (the constant part of rho b enters the
+// second-moment source).
+template <int S, bool GATHERED, bool HASK>
+__global__ void __launch_bounds__(TileFor<S>::type::NT) __attribute__((amdgpu_waves_per_eu(FUSED_WAVES_PER_EU)))
 k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
         typename Storage<S>::T *__restrict__ Fo, typename Storage<S>::T *__restrict__ Bo,
         const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
         StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag, FusedGeo fg) {
     using C = typename Storage<S>::C;
-    __shared__ C lds[3][NSRC * FNS];
+    using T = typename Storage<S>::T;
+    using TL = typename TileFor<S>::type;
+    constexpr int TX = TL::TX, TY = TL::TY, NS = TL::NS, NB2 = TL::NB2;
+    constexpr int NSTAGE = (NB2 + TL::NT - 1) / TL::NT;  // staging sites per thread
+    constexpr int SB = (int)sizeof(T);
+    __shared__ C lds[3][NSRC * NS];
+    __shared__ C bst[GATHERED ? 1 : 3][GATHERED ? 1 : NB * NB2];
+
+    Buf<S> bF, bB, bFo, bBo;
+    bF.init(F, Q, g.n);
+    bB.init(B, NB, g.n);
+    bFo.init(Fo, Q, g.n);
+    bBo.init(Bo, NB, g.n);
 
     // XCD-aware work-group numbering
     const int nblk = gridDim.x;
@@ -102,119 +244,195 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
     const int chunk = L / fg.tiles_y;
     const int z0 = chunk * fg.zchunk;
     const int z1 = min(z0 + fg.zchunk, g.nz);
+    const int nxy = g.nx * g.ny;
 
-    const int lx = threadIdx.x % FTX, ly = threadIdx.x / FTX;
-    const int x0 = tx * FTX, y0 = ty * FTY;
+    // --- per-thread offsets, computed once (xy part; the plane offset is added per plane) ---
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int x0 = tx * TX, y0 = ty * TY;
     const int gx = x0 + lx, gy = y0 + ly;
     const bool inside = gx < g.nx && gy < g.ny;
     const int wx = wrapc(gx, g.nx), wy = wrapc(gy, g.ny);
-
-    // ring site of this thread (second round), if any
-    const bool has_ring = threadIdx.x < FNH;
-    int rlx = 0, rly = 0;
-    {
-        const int h = threadIdx.x;
-        if (h < FHX) {
+    const int ixy = wy * g.nx + wx;
+    const int iidx = (ly + 1) * TL::HX + (lx + 1);
+    const int ibidx = (ly + 2) * TL::BX + (lx + 2);
+    // push targets: x and y offsets of the 3x3 neighbourhood (periodic)
+    int Xo[3], Yo[3];
+    Xo[0] = wx == 0 ? g.nx - 1 : wx - 1;
+    Xo[1] = wx;
+    Xo[2] = wx == g.nx - 1 ? 0 : wx + 1;
+    Yo[0] = (wy == 0 ? g.ny - 1 : wy - 1) * g.nx;
+    Yo[1] = wy * g.nx;
+    Yo[2] = (wy == g.ny - 1 ? 0 : wy + 1) * g.nx;
+    // ring sites (one per thread when the tile has 8 rows; general stride below)
+    constexpr int NRING = (TL::NH + TL::NT - 1) / TL::NT;
+    int rxy[NRING], rlidx[NRING], rbidx[NRING];
+#pragma unroll
+    for (int j = 0; j < NRING; j++) {
+        const int h = threadIdx.x + j * TL::NT;
+        int rlx = 0, rly = 0;
+        if (h < TL::HX) {
             rly = -1;
             rlx = h - 1;
-        } else if (h < 2 * FHX) {
-            rly = FTY;
-            rlx = h - FHX - 1;
-        } else if (h < 2 * FHX + FTY) {
+        } else if (h < 2 * TL::HX) {
+            rly = TY;
+            rlx = h - TL::HX - 1;
+        } else if (h < 2 * TL::HX + TY) {
             rlx = -1;
-            rly = h - 2 * FHX;
+            rly = h - 2 * TL::HX;
         } else {
-            rlx = FTX;
-            rly = h - 2 * FHX - FTY;
+            rlx = TX;
+            rly = h - 2 * TL::HX - TY;
         }
+        rxy[j] = wrapc(y0 + rly, g.ny) * g.nx + wrapc(x0 + rlx, g.nx);
+        rlidx[j] = (rly + 1) * TL::HX + (rlx + 1);
+        rbidx[j] = (rly + 2) * TL::BX + (rlx + 2);
     }
-    const int rwx = wrapc(x0 + rlx, g.nx), rwy = wrapc(y0 + rly, g.ny);
-    const int ridx = (rly + 1) * FHX + (rlx + 1);
-    const int iidx = (ly + 1) * FHX + (lx + 1);
+    // bbar* staging sites
+    int sxy[NSTAGE];
+#pragma unroll
+    for (int j = 0; j < NSTAGE; j++) {
+        const int r = threadIdx.x + j * TL::NT;
+        const int bx = r % TL::BX - 2, by = r / TL::BX - 2;
+        sxy[j] = wrapc(y0 + by, g.ny) * g.nx + wrapc(x0 + bx, g.nx);
+    }
 
-    SiteState<C> cur, nxt;
     const bool thin = g.nz <= 2;
 
-    // sources of plane p (march index, wrapped) into LDS slot `slot`, keeping the tile state
+    auto stage = [&](int q, int slot) {
+        if constexpr (!GATHERED) {
+            const int zo = wrapc(q, g.nz) * nxy;
+#pragma unroll
+            for (int j = 0; j < NSTAGE; j++) {
+                const int r = threadIdx.x + j * TL::NT;
+                if (r < NB2) {
+                    const int off = (zo + sxy[j]) * SB;
+                    Unroll<0, NB>::run([&](auto c) { bst[slot][c * NB2 + r] = bB.template loadf<c, Q>(off, cd); });
+                }
+            }
+        }
+    };
+    // slot of a staged plane q: (q - z0 + 6) % 3 when marching, q itself when nz <= 2
+    auto bslot = [&](int q) { return thin ? wrapc(q, g.nz) : (q - z0 + 6) % 3; };
+
+    // sources of plane p into LDS source slot `slot`, keeping the tile state
     auto fill = [&](int p, int slot, SiteState<C> &keep) {
-        const int wz = wrapc(p, g.nz);
-        source_site<S, GATHERED, true>(F, B, Tf, Tconst, g, k, cd, wx, wy, wz, lds[slot], iidx, keep);
-        // keep the two source evaluations apart: interleaving them doubles the loads in flight
-        // and the registers they hold
-        __builtin_amdgcn_sched_barrier(0);
-        if (has_ring) {
-            SiteState<C> dummy;
-            source_site<S, GATHERED, false>(F, B, Tf, Tconst, g, k, cd, rwx, rwy, wz, lds[slot], ridx, dummy);
+        const int zo = wrapc(p, g.nz) * nxy;
+        if constexpr (GATHERED) {
+            source_site_gathered<S, NS, true>(bF, bB, Tf, Tconst, k, cd, zo + ixy, lds[slot], iidx, keep);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < NRING; j++) {
+                if (threadIdx.x + j * TL::NT < TL::NH) {
+                    SiteState<C> dummy;
+                    source_site_gathered<S, NS, false>(bF, bB, Tf, Tconst, k, cd, zo + rxy[j], lds[slot], rlidx[j], dummy);
+                }
+            }
+        } else {
+            const C *bs[3] = {bst[bslot(p - 1)], bst[bslot(p)], bst[bslot(p + 1)]};
+            source_site_staged<S, TL, true>(bF, Tf, Tconst, k, cd, zo + ixy, ibidx, bs, lds[slot], iidx, keep);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < NRING; j++) {
+                if (threadIdx.x + j * TL::NT < TL::NH) {
+                    SiteState<C> dummy;
+                    source_site_staged<S, TL, false>(bF, Tf, Tconst, k, cd, zo + rxy[j], rbidx[j], bs, lds[slot],
+                                                     rlidx[j], dummy);
+                }
+            }
         }
     };
 
-    if (thin) {
-        fill(0, 0, cur);
-        if (g.nz == 2) fill(1, 1, nxt);
-    } else {
-        SiteState<C> dummy;
-        fill(z0 - 1, 2, dummy);  // slot of plane p is (p - z0 + 3) % 3
-        fill(z0, 0, cur);
-    }
-    __syncthreads();
-
     unsigned sat = 0;
-    for (int z = z0; z < z1; z++) {
-        int sm, s0, sp;  // slots of planes z-1, z, z+1
-        if (thin) {
-            s0 = z;
-            sm = sp = g.nz == 1 ? 0 : 1 - z;
-        } else {
+    // gradient, collision and push of plane z from the source slots (sm, s0, sp)
+    auto final_plane = [&](int z, int sm, int s0, int sp, SiteState<C> &cur) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (!inside) return;
+        const int wz = wrapc(z, g.nz);
+        const int zc = wz * nxy;
+        C d[Q];
+        load_pops<S>(bF, (zc + ixy) * SB, cd, d);  // issued early, consumed after the gradient
+        GradAcc<C> acc;
+        grad_init(acc);
+        const C *pm = lds[sm] + iidx, *p0 = lds[s0] + iidx, *pp = lds[sp] + iidx;
+        Unroll<1, Q>::run([&](auto I) {
+            constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
+            const C *pl = ez < 0 ? pm : (ez > 0 ? pp : p0);
+            constexpr int off = ey * TL::HX + ex;
+            C sv[NSRC];
+#pragma unroll
+            for (int c = 0; c < NSRC; c++) sv[c] = pl[c * NS + off];
+            grad_add<C, I, HASK>(acc, sv, k.K);
+            if constexpr (I % GRAD_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+        });
+        C Fv[3], Sv[6];
+        grad_finish(acc, Fv, Sv);
+        const PopMoments<C> m = pop_moments(d, k.rho_ref);
+        collide(d, cur.beta, m, Fv, Sv, cur.theta, k);
+        int Zo[3];
+        Zo[0] = (wz == 0 ? g.nz - 1 : wz - 1) * nxy;
+        Zo[1] = zc;
+        Zo[2] = (wz == g.nz - 1 ? 0 : wz + 1) * nxy;
+        Unroll<0, Q>::run([&](auto I) {
+            const int t = Zo[EZ[I] + 1] + Yo[EY[I] + 1] + Xo[EX[I] + 1];
+            bFo.template storef<I, 0>(t * SB, d[I], cd, sat);
+        });
+        const int so = (zc + ixy) * SB;
+        Unroll<0, NB>::run([&](auto c) { bBo.template storef<c, Q>(so, cur.beta[c], cd, sat); });
+    };
+
+    SiteState<C> sa, sb;
+    if (thin) {
+        for (int q = 0; q < g.nz; q++) stage(q, q);
+        __syncthreads();
+        fill(0, 0, sa);
+        if (g.nz == 2) fill(1, 1, sb);
+        __syncthreads();
+        final_plane(0, g.nz == 1 ? 0 : 1, 0, g.nz == 1 ? 0 : 1, sa);
+        if (g.nz == 2) final_plane(1, 0, 1, 0, sb);
+    } else {
+        stage(z0 - 2, bslot(z0 - 2));
+        stage(z0 - 1, bslot(z0 - 1));
+        stage(z0, bslot(z0));
+        __syncthreads();
+        fill(z0 - 1, 2, sb);  // source slot of plane p is (p - z0 + 3) % 3; sb is scratch here
+        __syncthreads();
+        stage(z0 + 1, bslot(z0 + 1));  // overwrites the slot of z0 - 2
+        __syncthreads();
+        fill(z0, 0, sa);
+        __syncthreads();
+        // one plane: stage z+2, sources of z+1 into `nxt`, then the final of z from `cur`
+        auto iter = [&](int z, SiteState<C> &cur, SiteState<C> &nxt) {
+            stage(z + 2, bslot(z + 2));  // slot of plane z-1, whose last gather was for plane z
+            __syncthreads();
             fill(z + 1, (z + 1 - z0 + 3) % 3, nxt);
             __syncthreads();
-            sm = (z - 1 - z0 + 3) % 3;
-            s0 = (z - z0) % 3;
-            sp = (z + 1 - z0) % 3;
+            final_plane(z, (z - 1 - z0 + 3) % 3, (z - z0) % 3, (z + 1 - z0) % 3, cur);
+            // the next staging overwrites the bbar* plane read by this plane's gathers, and the
+            // next fill the source plane read by this plane's gradients
+            __syncthreads();
+        };
+        for (int z = z0; z < z1; z++) {
+            iter(z, sa, sb);
+            sa = sb;
         }
-        __builtin_amdgcn_sched_barrier(0);
-        if (inside) {
-            // isotropic gradients of the sources over the 18 neighbours (LDS)
-            GradAcc<C> acc;
-            grad_init(acc);
-            Unroll<1, Q>::run([&](auto I) {
-                constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
-                const C *pl = lds[ez < 0 ? sm : (ez > 0 ? sp : s0)];
-                const int li = iidx + ey * FHX + ex;
-                C sv[NSRC];
-#pragma unroll
-                for (int c = 0; c < NSRC; c++) sv[c] = pl[c * FNS + li];
-                grad_add<C, I>(acc, sv, k.K);
-            });
-            C Fv[3], Sv[6];
-            grad_finish(acc, Fv, Sv);
-            collide(cur.d, cur.beta, cur.m, Fv, Sv, cur.theta, k);
-            const Nbr nb = make_nbr(wx, wy, wrapc(z, g.nz), g.nx, g.ny, g.nz);
-            Unroll<0, Q>::run([&](auto I) {
-                Storage<S>::store(Fo, (size_t)I * g.n + nb.at(EX[I], EY[I], EZ[I]), I, cur.d[I], cd, sat);
-            });
-            const int s = nb.at(0, 0, 0);
-#pragma unroll
-            for (int c = 0; c < NB; c++) Storage<S>::store(Bo, (size_t)c * g.n + s, Q + c, cur.beta[c], cd, sat);
-        }
-        cur = nxt;
-        __syncthreads();
     }
     if (sat) *flag = 1u;
 }
 
-inline FusedGeo fused_geometry(const Geo &g) {
+template <int S> inline FusedGeo fused_geometry(const Geo &g) {
+    using TL = typename TileFor<S>::type;
     FusedGeo fg;
-    fg.tiles_x = (g.nx + FTX - 1) / FTX;
-    fg.tiles_y = (g.ny + FTY - 1) / FTY;
+    fg.tiles_x = (g.nx + TL::TX - 1) / TL::TX;
+    fg.tiles_y = (g.ny + TL::TY - 1) / TL::TY;
     const int tiles = fg.tiles_x * fg.tiles_y;
     if (g.nz <= 2) {
         fg.nchunks = 1;
         fg.zchunk = g.nz;
         return fg;
     }
-    // enough work-groups to fill 256 CUs several times over, chunks of at least 8 planes
-    int want = (2048 + tiles - 1) / tiles;
-    int maxc = g.nz / 8 > 0 ? g.nz / 8 : 1;
+    // enough work-groups to fill the 256 CUs several times over, chunks of at least 16 planes
+    int want = (1024 + tiles - 1) / tiles;
+    int maxc = g.nz / 16 > 0 ? g.nz / 16 : 1;
     int nch = want < maxc ? want : maxc;
     if (nch < 1) nch = 1;
     fg.zchunk = (g.nz + nch - 1) / nch;
@@ -222,22 +440,32 @@ inline FusedGeo fused_geometry(const Geo &g) {
     return fg;
 }
 
-inline bool fused_supported(const Geo &) { return true; }
+// Every buffer-resource group (PPG planes) must stay below 4 GiB.
+template <int S> inline bool fused_supported_s(const Geo &g) {
+    return (unsigned long long)Buf<S>::PPG * (unsigned long long)g.n * sizeof(typename Storage<S>::T) < (1ull << 32);
+}
+inline bool fused_supported(const Geo &g) {
+    return fused_supported_s<0>(g);  // the strictest storage (8-byte) bounds them all
+}
 
 template <int S>
 int launch_fused(const typename Storage<S>::T *F, const typename Storage<S>::T *B, typename Storage<S>::T *Fo,
                  typename Storage<S>::T *Bo, const typename Storage<S>::C *Tf, typename Storage<S>::C Tconst,
                  const Geo &g, const StepConst<typename Storage<S>::C> &k, const Codec &cd, unsigned *flag,
                  bool gathered, hipStream_t stream) {
-    const FusedGeo fg = fused_geometry(g);
+    using TL = typename TileFor<S>::type;
+    const FusedGeo fg = fused_geometry<S>(g);
     const long long blocks = (long long)fg.tiles_x * fg.tiles_y * fg.nchunks;
     if (blocks > 2147483647LL) return -1;
-    if (gathered)
-        hipLaunchKernelGGL((k_fused<S, true>), dim3((unsigned)blocks), dim3(FNT), 0, stream, F, B, Fo, Bo, Tf, Tconst,
-                           g, k, cd, flag, fg);
-    else
-        hipLaunchKernelGGL((k_fused<S, false>), dim3((unsigned)blocks), dim3(FNT), 0, stream, F, B, Fo, Bo, Tf, Tconst,
-                           g, k, cd, flag, fg);
+    const dim3 grid((unsigned)blocks), block(TL::NT);
+    const bool hask = k.K != 0;
+    if (gathered) {
+        if (hask) hipLaunchKernelGGL((k_fused<S, true, true>), grid, block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg);
+        else hipLaunchKernelGGL((k_fused<S, true, false>), grid, block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg);
+    } else {
+        if (hask) hipLaunchKernelGGL((k_fused<S, false, true>), grid, block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg);
+        else hipLaunchKernelGGL((k_fused<S, false, false>), grid, block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg);
+    }
     return 0;
 }
 
