@@ -98,7 +98,8 @@ void codec_defaults(lbm_lattice *h) {
 
 // Power-of-two scale per field: the largest deviation maps to at most HMAX/16 (fp16), leaving
 // 16x headroom for growth before saturation.  A field that starts without deviation gets the
-// scale of a deviation of 1e-3 of its reference magnitude (1e-3 for bbar).
+// scale of a deviation of 1e-3 of its reference magnitude (1e-3 for bbar).  bfloat16 has the
+// exponent range of binary32, so its codes hold the deviations themselves (unit scale).
 void choose_scales(lbm_lattice *h, const double *absmax) {
     if (h->p.storage != LBM_F16DEV) {
         for (int k = 0; k < NFIELD; k++) h->codec.scale[k] = h->codec.inv[k] = 1.0f;

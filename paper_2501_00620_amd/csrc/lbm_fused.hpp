@@ -53,8 +53,9 @@ struct FusedGeo {
 };
 
 // Buffer addressing of an array of planes (n values each): one buffer resource (4 SGPRs) per
-// group of PPG planes, a 32-bit per-lane byte offset of the site, and the plane's byte offset
-// inside its group as the scalar offset.  No 64-bit per-lane address is ever formed, and a
+// group of PPG planes and a 32-bit per-lane byte offset (site offset plus the plane's offset
+// inside its group; the scalar-offset operand stays 0, since a uniform offset the compiler
+// keeps in a VGPR would otherwise be re-scalarised lane by lane).  No 64-bit per-lane address is ever formed, and a
 // group stays below 4 GiB for every lattice the fused kernel accepts.
 template <int S> struct Buf {
     using T = typename Storage<S>::T;
@@ -64,59 +65,58 @@ template <int S> struct Buf {
     __amdgpu_buffer_rsrc_t r[NG];
     int pb;  // plane bytes
 
+    // Every descriptor is assigned (groups past the last plane get an empty range), from base
+    // addresses passed through readfirstlane, so the compiler knows them to be wave-uniform and
+    // keeps them in SGPRs instead of looping over lanes.
     __device__ __forceinline__ void init(const T *base, int nplanes, int n) {
-        pb = n * (int)sizeof(T);
+        pb = __builtin_amdgcn_readfirstlane(n * (int)sizeof(T));
 #pragma unroll
         for (int g = 0; g < NG; g++) {
             const int np = nplanes - g * PPG;
-            if (np > 0) {
-                const unsigned bytes = (unsigned)(np < PPG ? np : PPG) * (unsigned)pb;
-                r[g] = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)g * PPG * n), (short)0, (int)bytes,
-                                                         0x00020000);
-            }
+            const unsigned bytes = np > 0 ? (unsigned)(np < PPG ? np : PPG) * (unsigned)pb : 0u;
+            const unsigned long long a = (unsigned long long)(base + (size_t)(np > 0 ? g : 0) * PPG * n);
+            const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
+            const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+            void *p = (void *)(((unsigned long long)hi << 32) | lo);
+            r[g] = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, (int)__builtin_amdgcn_readfirstlane((int)bytes),
+                                                     0x00020000);
         }
     }
-    template <int K> __device__ __forceinline__ C load(int off, const Codec &cd) const {
-        constexpr int g = K / PPG, j = K % PPG;
-        const __amdgpu_buffer_rsrc_t rs = r[g];
-        if constexpr (S == 0) {
-            auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, j * pb, 0);
-            return __builtin_bit_cast(double, v);
-        } else if constexpr (S == 1) {
-            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, j * pb, 0));
-        } else if constexpr (S == 2) {
-            return cd.scale[K] * half_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, j * pb, 0));
-        } else {
-            return cd.scale[K] * bf16_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, j * pb, 0));
-        }
-    }
-    // plane K of this array holds codec field F0 + K
+    // plane K of this array holds codec field F0 + K.  The plane's byte offset in its group goes
+    // to the scalar-offset operand through readfirstlane, so it is known to be wave-uniform.
     template <int K, int F0> __device__ __forceinline__ C loadf(int off, const Codec &cd) const {
         constexpr int g = K / PPG, j = K % PPG;
         const __amdgpu_buffer_rsrc_t rs = r[g];
+        const int so = __builtin_amdgcn_readfirstlane(j * pb);
         if constexpr (S == 0) {
-            auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, j * pb, 0);
+            auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, so, 0);
             return __builtin_bit_cast(double, v);
         } else if constexpr (S == 1) {
-            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, j * pb, 0));
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, so, 0));
         } else if constexpr (S == 2) {
-            return cd.scale[F0 + K] * half_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, j * pb, 0));
-        } else {
-            return cd.scale[F0 + K] * bf16_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, j * pb, 0));
+            return cd.scale[F0 + K] * half_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, so, 0));
+        } else {  // bf16 codes hold the deviation itself (unit scale)
+            return bf16_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, so, 0));
         }
     }
-    template <int K, int F0> __device__ __forceinline__ void storef(int off, C v, const Codec &cd, unsigned &sat) const {
+    // Stores a value; for 16-bit codes, amax collects |code| so that one comparison after the
+    // sweep detects overflow (an overflowing code is stored as +-inf and reported as RANGE).
+    template <int K, int F0> __device__ __forceinline__ void storef(int off, C v, const Codec &cd, float &amax) const {
         constexpr int g = K / PPG, j = K % PPG;
         const __amdgpu_buffer_rsrc_t rs = r[g];
+        const int so = __builtin_amdgcn_readfirstlane(j * pb);
         if constexpr (S == 0) {
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0)), v),
-                                                  rs, off, j * pb, 0);
+                                                  rs, off, so, 0);
         } else if constexpr (S == 1) {
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, j * pb, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, so, 0);
         } else if constexpr (S == 2) {
-            __builtin_amdgcn_raw_buffer_store_b16(float_to_half_bits(v * cd.inv[F0 + K], sat), rs, off, j * pb, 0);
+            const float h = v * cd.inv[F0 + K];
+            amax = fmaxf(amax, fabsf(h));
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)h), rs, off, so, 0);
         } else {
-            __builtin_amdgcn_raw_buffer_store_b16(float_to_bf16_bits(v * cd.inv[F0 + K], sat), rs, off, j * pb, 0);
+            amax = fmaxf(amax, fabsf(v));
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (__bf16)v), rs, off, so, 0);
         }
     }
 };
@@ -342,7 +342,7 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
         }
     };
 
-    unsigned sat = 0;
+    float amax = 0.0f;  // largest |16-bit code| stored (overflow check)
     // gradient, collision and push of plane z from the source slots (sm, s0, sp)
     auto final_plane = [&](int z, int sm, int s0, int sp, SiteState<C> &cur) {
         __builtin_amdgcn_sched_barrier(0);
@@ -374,10 +374,10 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
         Zo[2] = (wz == g.nz - 1 ? 0 : wz + 1) * nxy;
         Unroll<0, Q>::run([&](auto I) {
             const int t = Zo[EZ[I] + 1] + Yo[EY[I] + 1] + Xo[EX[I] + 1];
-            bFo.template storef<I, 0>(t * SB, d[I], cd, sat);
+            bFo.template storef<I, 0>(t * SB, d[I], cd, amax);
         });
         const int so = (zc + ixy) * SB;
-        Unroll<0, NB>::run([&](auto c) { bBo.template storef<c, Q>(so, cur.beta[c], cd, sat); });
+        Unroll<0, NB>::run([&](auto c) { bBo.template storef<c, Q>(so, cur.beta[c], cd, amax); });
     };
 
     SiteState<C> sa, sb;
@@ -416,7 +416,11 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
             sa = sb;
         }
     }
-    if (sat) *flag = 1u;
+    if constexpr (S == 2) {
+        if (!(amax <= 65504.0f)) *flag = 1u;
+    } else if constexpr (S == 3) {
+        if (!(amax <= 3.3895e38f)) *flag = 1u;
+    }
 }
 
 template <int S> inline FusedGeo fused_geometry(const Geo &g) {
