@@ -140,6 +140,77 @@ const char *lbm_last_error(void);
 /* Steps taken since the last set_fields / set_state. */
 long lbm_steps_done(lbm_handle h);
 
+/* Device bytes a lattice with these parameters occupies (what lbm_create allocates). */
+size_t lbm_lattice_bytes(const lbm_params *p);
+
+/* ---------------------------------------------------------------------------------------------
+ * Serving: continuous batching of many independent lattices on one GPU.
+ *
+ * Requests (each an initial state and a step count) are queued by lbm_server_submit and
+ * admitted, first fit in arrival order, whenever their lattice fits the device-memory budget
+ * next to the lattices already resident.  All resident lattices advance together: a persistent
+ * kernel walks a packed index of (lattice, tile) pairs and applies the same step as lbm_step to
+ * each tile (the first step of a request runs at admission), and bundles of K such steps are
+ * replayed from one captured HIP graph.  A lattice whose steps are done leaves the bundle at
+ * its own step count, is health-checked, its moments (as lbm_get_moments) are copied to host
+ * memory, and its device memory is released for the queue.  Requests that arrive while others
+ * run are admitted between bundles.  A request's result does not depend on what else is being
+ * served (the per-site arithmetic is the same as stepping it alone).
+ *
+ * The server runs a worker thread; its calls are thread-safe.  Every served lattice uses the
+ * server's storage; F32, F16DEV and BF16DEV are supported.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct lbm_server *lbm_server_handle;
+
+#define LBM_REQ_QUEUED 0  /* waiting for device memory                          */
+#define LBM_REQ_RUNNING 1 /* resident, being stepped                             */
+#define LBM_REQ_DONE 2    /* finished; results can be fetched                    */
+#define LBM_REQ_FAILED 3  /* rejected or diverged; see lbm_server_error           */
+
+typedef struct {
+    size_t hbm_budget_bytes; /* device memory the resident lattices may occupy together   */
+    int bundle_steps;        /* K, steps per captured graph replay (>= 1)                  */
+    int storage;             /* lbm_storage of the served lattices: F32, F16DEV, BF16DEV    */
+    int max_lattices;        /* most lattices resident at once (descriptor table size)     */
+    int health_every;        /* bundles between health checks of running lattices (0: only
+                                at completion)                                            */
+} lbm_server_params;
+
+/* Create a server on the current device and the given HIP stream (NULL: a stream of its own).
+ * Errors: ARG, OOM, HIP. */
+int lbm_server_create(const lbm_server_params *p, void *hip_stream, lbm_server_handle *out);
+
+/* Queue a request.  p->storage is ignored (the server's storage is used).  rho (n), u (3n) and
+ * T (n) are host arrays of `dtype`; they are copied before the call returns.  n_steps >= 1.
+ * *req_id receives the request's id.  Errors: ARG (bad parameters, or a lattice larger than
+ * the whole budget). */
+int lbm_server_submit(lbm_server_handle s, const lbm_params *p, const void *rho, const void *u, const void *T,
+                      int dtype, long n_steps, long *req_id);
+
+/* Status of a request and its times in seconds on a monotonic clock: times[0] submitted,
+ * times[1] admitted (0 if not yet), times[2] finished (0 if not yet). */
+int lbm_server_poll(lbm_server_handle s, long req_id, int *status, double times[3]);
+
+/* Block until the request is DONE or FAILED, or timeout_s elapses (returns LBM_ERR_BUSY). */
+int lbm_server_wait(lbm_server_handle s, long req_id, double timeout_s);
+
+/* Copy a finished request's moments (rho n, u 3n, T n of `dtype`, host memory; any may be
+ * NULL).  Errors: STATE if not DONE. */
+int lbm_server_fetch(lbm_server_handle s, long req_id, void *rho, void *u, void *T, int dtype);
+
+/* Forget a finished request (frees its host copy of the results). */
+int lbm_server_release(lbm_server_handle s, long req_id);
+
+/* Message of a FAILED request. */
+const char *lbm_server_error(lbm_server_handle s, long req_id);
+
+/* Counters: out[0] resident bytes, [1] running, [2] queued, [3] done, [4] failed, [5] bundles
+ * run, [6] lattice updates done by bundles, [7] seconds spent in bundles (device + sync). */
+int lbm_server_stats(lbm_server_handle s, double out[8]);
+
+/* Stop the worker (running requests are abandoned) and free everything. */
+void lbm_server_destroy(lbm_server_handle s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_fused.hpp"
+#include "lbm_internal.hpp"
 #include "lbm_kernels.hpp"
 
 using namespace lbm;
@@ -31,6 +32,17 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
+}  // namespace
+
+namespace lbm {
+int set_error(int code, const char *msg) {
+    g_err = msg;
+    return code;
+}
+}  // namespace lbm
+
+namespace {
+
 #define HIP_TRY(expr)                                                                         \
     do {                                                                                      \
         hipError_t e_ = (expr);                                                               \
@@ -42,25 +54,8 @@ size_t compute_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
 }  // namespace
 
-struct lbm_lattice {
-    lbm_params p{};
-    hipStream_t stream = nullptr;
-    int n = 0;
-    void *F[2] = {nullptr, nullptr};
-    void *B[2] = {nullptr, nullptr};
-    void *src = nullptr;
-    void *Tf = nullptr;       // ISO temperature field (compute type), or null when uniform
-    double Tconst = 0.0;      // ISO uniform temperature, stored as theta = T - T_ref
-    int cur = 0;
-    bool gathered = true;
-    bool has_state = false;
-    long steps = 0;
-    Codec codec{};
-    double *partial = nullptr;  // 2 * RED_MAX_BLOCKS * RED_K (sum and max partials)
-    double *red_out = nullptr;  // RED_K
-    unsigned *flag = nullptr;   // saturation flag
-    int kernel = 0;
-};
+
+
 
 namespace {
 
@@ -263,6 +258,14 @@ int lbm_set_kernel(lbm_handle h, int kernel) {
 }
 
 long lbm_steps_done(lbm_handle h) { return h ? h->steps : -1; }
+
+size_t lbm_lattice_bytes(const lbm_params *p) {
+    if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1 || p->storage < 0 || p->storage > 3) return 0;
+    const size_t n = (size_t)p->nx * p->ny * p->nz;
+    return 2 * (size_t)NFIELD * store_bytes(p->storage) * n + NSRC * compute_bytes(p->storage) * n +
+           sizeof(double) * (2 * RED_MAX_BLOCKS * RED_K + RED_K) + sizeof(unsigned) +
+           (p->mode == LBM_ISO ? compute_bytes(p->storage) * n : 0);
+}
 
 int lbm_sync(lbm_handle h) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
@@ -529,7 +532,7 @@ int lbm_set_state(lbm_handle h, const void *F, const void *b, int on_device) {
     const int rb = red_blocks(h->n);
     double absmax[NFIELD + 1];
     codec_defaults(h);
-    hipLaunchKernelGGL(k_absmax_state, dim3(rb), dim3(BLOCK), 0, h->stream, dF, dB, g, h->codec, h->partial);
+    hipLaunchKernelGGL(k_absmax_state<0>, dim3(rb), dim3(BLOCK), 0, h->stream, dF, dB, g, h->codec, h->partial);
     int rc = check_launch();
     if (!rc) rc = finish_reduction<true>(h, rb, NFIELD + 1, absmax);
     if (!rc && absmax[NFIELD] > 0) rc = fail(LBM_ERR_ARG, "state contains non-finite values");

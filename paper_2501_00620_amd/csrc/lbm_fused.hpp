@@ -206,19 +206,18 @@ __device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typen
     }
 }
 
-#ifndef FUSED_WAVES_PER_EU
-#define FUSED_WAVES_PER_EU 2
-#endif
-
-// Occupancy: the LDS (about 130 KB of 160 KB for float) admits one 512-thread work-group per
-// CU, i.e. two waves per SIMD.  HASK: T_ref != 1/3 (the constant part of rho b enters the
-// second-moment source).
+// One work-group sweeps tile (tx, ty) of z chunk `chunk` for one step.  Shared by the
+// single-lattice kernel and the multi-lattice serving kernel.  HASK: T_ref != 1/3 (the constant
+// part of rho b enters the second-moment source).  amax collects |16-bit codes| stored.
 template <int S, bool GATHERED, bool HASK>
-__global__ void __launch_bounds__(TileFor<S>::type::NT) __attribute__((amdgpu_waves_per_eu(FUSED_WAVES_PER_EU)))
-k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
-        typename Storage<S>::T *__restrict__ Fo, typename Storage<S>::T *__restrict__ Bo,
-        const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
-        StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag, FusedGeo fg) {
+__device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restrict__ F,
+                                           const typename Storage<S>::T *__restrict__ B,
+                                           typename Storage<S>::T *__restrict__ Fo,
+                                           typename Storage<S>::T *__restrict__ Bo,
+                                           const typename Storage<S>::C *__restrict__ Tf,
+                                           typename Storage<S>::C Tconst, const Geo &g,
+                                           const StepConst<typename Storage<S>::C> &k, const Codec &cd,
+                                           const FusedGeo &fg, int tx, int ty, int chunk, float &amax) {
     using C = typename Storage<S>::C;
     using T = typename Storage<S>::T;
     using TL = typename TileFor<S>::type;
@@ -234,14 +233,6 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
     bFo.init(Fo, Q, g.n);
     bBo.init(Bo, NB, g.n);
 
-    // XCD-aware work-group numbering
-    const int nblk = gridDim.x;
-    int L = blockIdx.x;
-    if ((nblk & 7) == 0) L = (L & 7) * (nblk >> 3) + (L >> 3);
-    const int tx = L % fg.tiles_x;
-    L /= fg.tiles_x;
-    const int ty = L % fg.tiles_y;
-    const int chunk = L / fg.tiles_y;
     const int z0 = chunk * fg.zchunk;
     const int z1 = min(z0 + fg.zchunk, g.nz);
     const int nxy = g.nx * g.ny;
@@ -342,7 +333,6 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
         }
     };
 
-    float amax = 0.0f;  // largest |16-bit code| stored (overflow check)
     // gradient, collision and push of plane z from the source slots (sm, s0, sp)
     auto final_plane = [&](int z, int sm, int s0, int sp, SiteState<C> &cur) {
         __builtin_amdgcn_sched_barrier(0);
@@ -416,11 +406,43 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
             sa = sb;
         }
     }
+    // the LDS may be reused at once by the next tile of a persistent work-group
+    __syncthreads();
+}
+
+// Overflow check of the 16-bit codes a thread stored.
+template <int S> __device__ __forceinline__ void report_range(float amax, unsigned *flag) {
     if constexpr (S == 2) {
         if (!(amax <= 65504.0f)) *flag = 1u;
     } else if constexpr (S == 3) {
         if (!(amax <= 3.3895e38f)) *flag = 1u;
     }
+}
+
+#ifndef FUSED_WAVES_PER_EU
+#define FUSED_WAVES_PER_EU 2
+#endif
+
+// Occupancy: the LDS (about 130 KB of 160 KB for float) admits one 512-thread work-group per
+// CU, i.e. two waves per SIMD.
+template <int S, bool GATHERED, bool HASK>
+__global__ void __launch_bounds__(TileFor<S>::type::NT) __attribute__((amdgpu_waves_per_eu(FUSED_WAVES_PER_EU)))
+k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
+        typename Storage<S>::T *__restrict__ Fo, typename Storage<S>::T *__restrict__ Bo,
+        const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
+        StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag, FusedGeo fg) {
+    // XCD-aware work-group numbering: the work-groups of one XCD (block index mod 8) take
+    // neighbouring tiles of the same z chunk
+    const int nblk = gridDim.x;
+    int L = blockIdx.x;
+    if ((nblk & 7) == 0) L = (L & 7) * (nblk >> 3) + (L >> 3);
+    const int tx = L % fg.tiles_x;
+    L /= fg.tiles_x;
+    const int ty = L % fg.tiles_y;
+    const int chunk = L / fg.tiles_y;
+    float amax = 0.0f;
+    sweep_tile<S, GATHERED, HASK>(F, B, Fo, Bo, Tf, Tconst, g, k, cd, fg, tx, ty, chunk, amax);
+    report_range<S>(amax, flag);
 }
 
 template <int S> inline FusedGeo fused_geometry(const Geo &g) {

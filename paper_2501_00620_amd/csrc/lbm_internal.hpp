@@ -1,0 +1,33 @@
+// lbm_internal.hpp -- the lattice object behind an lbm_handle, shared by the C-ABI and the
+// serving runtime (both in liblbm.so).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/lbm.h"
+#include "lbm_device.hpp"
+
+struct lbm_lattice {
+    lbm_params p{};
+    hipStream_t stream = nullptr;
+    int n = 0;
+    void *F[2] = {nullptr, nullptr};
+    void *B[2] = {nullptr, nullptr};
+    void *src = nullptr;
+    void *Tf = nullptr;       // ISO temperature field (compute type), or null when uniform
+    double Tconst = 0.0;      // ISO uniform temperature, stored as theta = T - T_ref
+    int cur = 0;
+    bool gathered = true;
+    bool has_state = false;
+    long steps = 0;
+    lbm::Codec codec{};
+    double *partial = nullptr;  // 2 * RED_MAX_BLOCKS * RED_K (sum and max partials)
+    double *red_out = nullptr;  // RED_K
+    unsigned *flag = nullptr;   // saturation flag
+    int kernel = 0;
+};
+
+namespace lbm {
+// Sets the calling thread's lbm_last_error() message; returns code.
+int set_error(int code, const char *msg);
+}  // namespace lbm

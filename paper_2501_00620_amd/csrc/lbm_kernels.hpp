@@ -387,7 +387,9 @@ k_absmax_fields(const IN *__restrict__ rho, const IN *__restrict__ u, const IN *
     block_reduce_store<NFIELD + 1, true>(v, partial);
 }
 
-// Same for a given double state (set_state); slot 25 counts non-finite values.
+// Same for a given double state (set_state); slot 25 counts non-finite values.  (A template so
+// that every translation unit including this header may instantiate it.)
+template <int UNUSED = 0>
 __global__ void __launch_bounds__(BLOCK)
 k_absmax_state(const double *__restrict__ F, const double *__restrict__ B, Geo g, Codec cd, double *__restrict__ partial) {
     double v[NFIELD + 1];

@@ -54,7 +54,26 @@ SIGNATURES = {
     "lbm_destroy": ([C.c_void_p], None),
     "lbm_last_error": ([], C.c_char_p),
     "lbm_steps_done": ([C.c_void_p], C.c_long),
+    "lbm_lattice_bytes": ([C.c_void_p], C.c_size_t),
+    "lbm_server_create": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int),
+    "lbm_server_submit": ([C.c_void_p, C.POINTER(lbm_params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                           C.c_long, C.POINTER(C.c_long)], C.c_int),
+    "lbm_server_poll": ([C.c_void_p, C.c_long, C.POINTER(C.c_int), C.POINTER(C.c_double)], C.c_int),
+    "lbm_server_wait": ([C.c_void_p, C.c_long, C.c_double], C.c_int),
+    "lbm_server_fetch": ([C.c_void_p, C.c_long, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
+    "lbm_server_release": ([C.c_void_p, C.c_long], C.c_int),
+    "lbm_server_error": ([C.c_void_p, C.c_long], C.c_char_p),
+    "lbm_server_stats": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
+    "lbm_server_destroy": ([C.c_void_p], None),
 }
+
+
+class lbm_server_params(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("bundle_steps", C.c_int), ("storage", C.c_int),
+                ("max_lattices", C.c_int), ("health_every", C.c_int)]
+
+
+REQ_STATUS = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
 
 def load_library(path=LIB_PATH):
@@ -235,3 +254,93 @@ class Lattice:
     @property
     def steps_done(self):
         return int(_lib.lbm_steps_done(self._h))
+
+
+def lattice_bytes(nx, ny, nz, storage="f32", mode="thermal"):
+    """Device bytes a lattice of this shape and storage occupies."""
+    lib = load_library()
+    p = lbm_params(int(nx), int(ny), int(nz), 1.0, 1.0 / 3.0, 1.0, STORAGE[storage], MODE[mode])
+    return int(lib.lbm_lattice_bytes(C.byref(p)))
+
+
+class Server:
+    """Continuous batching of many independent lattices (see include/lbm.h, lbm_server_*).
+
+    Requests are submitted from host arrays and served by a worker thread inside the library;
+    results come back as host (numpy) arrays."""
+
+    def __init__(self, budget_bytes, bundle_steps=50, storage="f32", max_lattices=1024, health_every=0):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("liblbm needs a HIP device (torch.cuda.is_available() is False)")
+        lib = load_library()
+        p = lbm_server_params(int(budget_bytes), int(bundle_steps), STORAGE[storage], int(max_lattices),
+                              int(health_every))
+        h = C.c_void_p()
+        _check(lib.lbm_server_create(C.byref(p), None, C.byref(h)))
+        self._h = h
+        self.storage = storage
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lbm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, rho, u, T, tau, steps, mode="thermal", T_ref=1.0 / 3.0, rho_ref=1.0):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        nz, ny, nx = rho.shape
+        u = np.ascontiguousarray(np.broadcast_to(u, (3, nz, ny, nx)), dtype=np.float64)
+        T = np.ascontiguousarray(np.broadcast_to(T, (nz, ny, nx)), dtype=np.float64)
+        p = lbm_params(nx, ny, nz, float(tau), float(T_ref), float(rho_ref), STORAGE[self.storage], MODE[mode])
+        rid = C.c_long()
+        _check(_lib.lbm_server_submit(self._h, C.byref(p), rho.ctypes.data_as(C.c_void_p),
+                                      u.ctypes.data_as(C.c_void_p), T.ctypes.data_as(C.c_void_p), 0,
+                                      int(steps), C.byref(rid)))
+        self.shapes[rid.value] = (nz, ny, nx)
+        return rid.value
+
+    def poll(self, rid):
+        """(status, t_submit, t_admit, t_done); times in seconds on a monotonic clock."""
+        st = C.c_int()
+        t = (C.c_double * 3)()
+        _check(_lib.lbm_server_poll(self._h, int(rid), C.byref(st), t))
+        return REQ_STATUS[st.value], t[0], t[1], t[2]
+
+    def wait(self, rid, timeout=120.0):
+        _check(_lib.lbm_server_wait(self._h, int(rid), float(timeout)))
+        return self.poll(rid)[0]
+
+    def fetch(self, rid):
+        shape = self.shapes[rid]
+        rho = np.empty(shape)
+        u = np.empty((3,) + shape)
+        T = np.empty(shape)
+        _check(_lib.lbm_server_fetch(self._h, int(rid), rho.ctypes.data_as(C.c_void_p),
+                                     u.ctypes.data_as(C.c_void_p), T.ctypes.data_as(C.c_void_p), 0))
+        return rho, u, T
+
+    def release(self, rid):
+        _check(_lib.lbm_server_release(self._h, int(rid)))
+        self.shapes.pop(rid, None)
+
+    def error(self, rid):
+        return _lib.lbm_server_error(self._h, int(rid)).decode()
+
+    def stats(self):
+        out = (C.c_double * 8)()
+        _check(_lib.lbm_server_stats(self._h, out))
+        keys = ["resident_bytes", "running", "queued", "done", "failed", "bundles", "lattice_updates", "busy_s"]
+        return dict(zip(keys, out[:]))

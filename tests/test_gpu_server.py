@@ -1,0 +1,118 @@
+"""Serving: many independent lattices batched on one GPU (lbm_server_* in include/lbm.h).
+
+- each request's result in the mix equals the same request stepped alone (bitwise: the
+  per-site arithmetic does not depend on what else is resident), also when a small memory
+  budget forces requests to queue and be admitted while others run;
+- a request that cannot start (non-finite input) or that diverges is reported FAILED without
+  disturbing the others;
+- the memory budget is enforced at submission for a lattice that could never fit;
+- 16-bit deviation storage is served the same way.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2501_00620_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def lbm():
+    from paper_2501_00620_amd import lbm as m
+    return m
+
+
+def alone(fields, tau, steps, storage, mode="thermal"):
+    rho, u, T = fields
+    nz, ny, nx = rho.shape
+    g = lbm().Lattice(nx, ny, nz, tau, storage=storage, mode=mode, kernel="fused")
+    g.set_fields(rho, u, T)
+    g.step(steps)
+    r, uu, TT = g.moments()
+    return r.cpu().numpy(), uu.cpu().numpy(), TT.cpu().numpy()
+
+
+def requests(seed, n):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        if k % 3 == 2:
+            d = int(rng.integers(12, 24))
+            f = wl.fourier_fields(d + 3, d, d - 2, seed=int(rng.integers(1 << 30)), u_max=0.2)
+        else:
+            f = wl.riemann2d_request(rng, n=int(rng.integers(40, 140)))
+        steps = int(rng.integers(5, 130))
+        tau = float(rng.uniform(0.6, 1.0))
+        out.append((f, tau, steps))
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16dev", "f16dev"])
+def test_mix_equals_alone_with_queueing(storage):
+    L = lbm()
+    reqs = requests(7, 9)
+    biggest = max(L.lattice_bytes(*f[0].shape[::-1], storage=storage) for f, _, _ in reqs)
+    # room for about two lattices: the rest must wait and be admitted as others finish
+    with L.Server(budget_bytes=int(2.2 * biggest), bundle_steps=16, storage=storage) as srv:
+        ids = []
+        for f, tau, steps in reqs:
+            ids.append(srv.submit(*f, tau=tau, steps=steps))
+            time.sleep(0.002)
+        for rid in ids:
+            assert srv.wait(rid, timeout=120) == "done", srv.error(rid)
+        st = srv.stats()
+        assert st["done"] == len(reqs) and st["failed"] == 0 and st["resident_bytes"] == 0
+        admits = sorted(srv.poll(r)[2] for r in ids)
+        dones = sorted(srv.poll(r)[3] for r in ids)
+        assert admits[-1] > dones[0]  # some request was admitted after another had finished
+        for rid, (f, tau, steps) in zip(ids, reqs):
+            got = srv.fetch(rid)
+            ref = alone(f, tau, steps, storage)
+            for a, b in zip(got, ref):
+                np.testing.assert_array_equal(a, b)
+
+
+def test_failures_are_isolated():
+    L = lbm()
+    good = wl.riemann2d_request(np.random.default_rng(1), n=64)
+    nan = wl.riemann2d_request(np.random.default_rng(2), n=48)
+    nan[0][0, 3, 5] = np.nan
+    rho, u, T = wl.fourier_fields(20, 18, 1, seed=3, u_max=0.2)
+    u = u.copy()
+    u[0] = 0.9  # beyond the positivity bound: diverges
+    with L.Server(budget_bytes=1 << 30, bundle_steps=10, storage="f32") as srv:
+        rg = srv.submit(*good, tau=0.8, steps=60)
+        rn = srv.submit(*nan, tau=0.8, steps=60)
+        rb = srv.submit(rho, u, T * 0.1, tau=0.01, steps=300)
+        assert srv.wait(rg) == "done"
+        assert srv.wait(rn) == "failed" and "admission" in srv.error(rn)
+        assert srv.wait(rb) == "failed" and "diverged" in srv.error(rb)
+        for a, b in zip(srv.fetch(rg), alone(good, 0.8, 60, "f32")):
+            np.testing.assert_array_equal(a, b)
+        with pytest.raises(L.LBMError):
+            srv.fetch(rn)
+
+
+def test_budget_is_enforced_at_submission():
+    L = lbm()
+    f = wl.riemann2d_request(np.random.default_rng(4), n=128)
+    need = L.lattice_bytes(128, 128, 1, storage="f32")
+    with L.Server(budget_bytes=need // 2, bundle_steps=8, storage="f32") as srv:
+        with pytest.raises(L.LBMError) as e:
+            srv.submit(*f, tau=0.8, steps=10)
+        assert e.value.name == "ARG"
+
+
+def test_iso_mode_and_single_step_requests():
+    L = lbm()
+    rho, u, T = wl.fourier_fields(33, 17, 5, seed=9, u_max=0.2)
+    with L.Server(budget_bytes=1 << 30, bundle_steps=7, storage="f32") as srv:
+        r1 = srv.submit(rho, u, T, tau=0.7, steps=1)
+        r2 = srv.submit(rho, u, T, tau=0.7, steps=23, mode="iso")
+        assert srv.wait(r1) == "done" and srv.wait(r2) == "done"
+        for a, b in zip(srv.fetch(r1), alone((rho, u, T), 0.7, 1, "f32")):
+            np.testing.assert_array_equal(a, b)
+        for a, b in zip(srv.fetch(r2), alone((rho, u, T), 0.7, 23, "f32", mode="iso")):
+            np.testing.assert_array_equal(a, b)
