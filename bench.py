@@ -12,6 +12,12 @@ Also reported on the same JSON line:
                 sources, else null;
   variants      the 2000-step run in FP64, FP32, FP16- and BF16-deviation storage: MLUPS and the
                 relative L2 error of rho, u, T against the FP64-storage run, kinetic-energy decay;
+  served        the served batch: 512 independent four-quadrant Riemann problems (n x n x 1,
+                n uniform in [64, 512], 2000 steps each) arriving as a Poisson stream at 50/s,
+                admitted by a 4 GiB device-memory budget, in FP32 and FP16/BF16-deviation
+                storage; p50/p99 time-to-result (per run and over the requests every storage
+                completed), aggregate MLUPS, failed requests with their reasons (strong
+                four-quadrant problems leave the scheme's stability region and diverge);
   cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded sample (a 48^3
                 Taylor-Green vortex for ~10 s).
 
@@ -33,11 +39,16 @@ BYTES_PER_VALUE = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
 VALUES_PER_LUP = 2 * (19 + 6)
 
 
+# The sources that define the fused sweep kernel and its compile flags: PMC counters taken on
+# other sources do not describe the kernel being timed.
+KERNEL_SOURCES = ("paper_2501_00620_amd/csrc/lbm_device.hpp", "paper_2501_00620_amd/csrc/lbm_fused.hpp",
+                  "paper_2501_00620_amd/build.py")
+
+
 def source_hash():
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2501_00620_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -101,8 +112,81 @@ def run_variants(n, steps, tau, mach, every=500):
         else:
             rec["rel_l2_vs_f64"] = {"rho": rel_l2(r, ref[0]), "u": rel_l2(u, ref[1]), "T": rel_l2(T, ref[2])}
         out[storage] = rec
+        print(f"[bench] variant {storage}: {rec['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         del lat
         torch.cuda.empty_cache()
+    return out
+
+
+def serving_requests(n_requests, rate, seed):
+    """Arrival times, grid edges and field seeds of the served batch (fixed by `seed`)."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+    sizes = rng.integers(64, 513, size=n_requests)
+    field_seeds = rng.integers(0, 1 << 62, size=n_requests)
+    return arrivals, sizes, field_seeds
+
+
+def run_serving(storage, n_requests=512, rate=50.0, steps=2000, budget=4 << 30, bundle=50, seed=2024, tau=0.8):
+    """Served batch: independent n x n x 1 four-quadrant Riemann problems, n uniform in
+    [64, 512], Poisson arrivals at `rate` per second, admitted by a device-memory budget.
+    Returns p50/p99 time-to-result, aggregate MLUPS over the whole run, and per-request
+    outcomes (latency, or the reason a request failed)."""
+    import numpy as np
+    from paper_2501_00620_amd import lbm, workloads
+    arrivals, sizes, field_seeds = serving_requests(n_requests, rate, seed)
+    ids = []
+    with lbm.Server(budget_bytes=budget, bundle_steps=bundle, storage=storage, health_every=10) as srv:
+        t0 = time.perf_counter()
+        for k in range(n_requests):
+            while time.perf_counter() - t0 < arrivals[k]:
+                time.sleep(min(0.002, max(0.0, arrivals[k] - (time.perf_counter() - t0))))
+            f = workloads.riemann2d_request(np.random.Generator(np.random.PCG64(int(field_seeds[k]))), n=int(sizes[k]))
+            ids.append(srv.submit(*f, tau=tau, steps=steps))
+        status = [srv.wait(r, timeout=600) for r in ids]
+        times = np.array([srv.poll(r)[1:] for r in ids])
+        errors = [srv.error(r) if s_ != "done" else "" for r, s_ in zip(ids, status)]
+        st = srv.stats()
+    ok = np.array([s_ == "done" for s_ in status])
+    print(f"[bench] served {storage}: {int(ok.sum())}/{n_requests} done", file=sys.stderr, flush=True)
+    latency = times[:, 2] - times[:, 0]
+    wait = times[ok, 1] - times[ok, 0]
+    span = times[ok, 2].max() - times[:, 0].min()
+    lups = float((sizes[ok].astype(np.float64) ** 2).sum() * steps)
+    reasons = {}
+    for e in errors:
+        if e:
+            key = e.split(":")[0]
+            reasons[key] = reasons.get(key, 0) + 1
+    rec = {"requests": n_requests, "done": int(ok.sum()), "failed": int((~ok).sum()),
+           "failure_reasons": reasons,
+           "p50_s": float(np.percentile(latency[ok], 50)), "p99_s": float(np.percentile(latency[ok], 99)),
+           "p50_queue_wait_s": float(np.percentile(wait, 50)), "p99_queue_wait_s": float(np.percentile(wait, 99)),
+           "aggregate_mlups": lups / span / 1e6, "span_s": float(span),
+           "bundle_busy_mlups": st["lattice_updates"] / max(st["busy_s"], 1e-9) / 1e6,
+           "workload": f"{n_requests} four-quadrant Riemann problems n x n x 1, n ~ U[64,512], tau {tau}, "
+                       f"{steps} steps, Poisson {rate}/s, budget {budget / 2**30:.0f} GiB, bundle {bundle} steps"}
+    return rec, ok, latency
+
+
+def run_served_comparison(storages=("f32", "f16dev", "bf16dev"), **kw):
+    """The served batch once per storage.  Requests that diverge are reported failed, and which
+    ones do depends on the storage precision, so beside each run's own percentiles the latency is
+    also given over the requests that completed under every storage."""
+    import numpy as np
+    out, oks, lats = {}, [], []
+    for st in storages:
+        rec, ok, lat = run_serving(st, **kw)
+        out[st] = rec
+        oks.append(ok)
+        lats.append(lat)
+    common = np.logical_and.reduce(oks)
+    for st, ok, lat in zip(storages, oks, lats):
+        out[st]["failed_also_in_" + storages[0]] = int((~ok & ~oks[0]).sum())
+        out[st]["common_requests"] = int(common.sum())
+        out[st]["p50_s_common"] = float(np.percentile(lat[common], 50))
+        out[st]["p99_s_common"] = float(np.percentile(lat[common], 99))
     return out
 
 
@@ -148,6 +232,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the precision variants and the CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-only", action="store_true", help="run only the served-batch workload")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -164,12 +250,16 @@ def main():
         return
 
     from paper_2501_00620_amd import lbm, workloads
+    if args.serve_only:
+        print(json.dumps({"served": run_served_comparison(n_requests=args.serve_requests)}))
+        return
     n, tau, mach = args.n, 0.55, 0.5
     rho, u, T = workloads.taylor_green(n, mach=mach)
     lat = lbm.Lattice(n, n, n, tau, storage=args.storage, kernel=args.kernel)
     lat.set_fields(rho, u, T)
     torch.cuda.synchronize()
     secs = timed_steps(lat, args.steps, args.warmup)
+    print(f"[bench] timed {args.steps} steps: {secs * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
     health = lat.health()
     sites = n ** 3
     ms_per_step = secs * 1e3 / args.steps
@@ -198,6 +288,7 @@ def main():
     }
     if not args.quick:
         line["variants"] = run_variants(n, args.variant_steps, tau, mach)
+        line["served"] = run_served_comparison(n_requests=args.serve_requests)
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     else:
         line["cpu_baseline"] = None

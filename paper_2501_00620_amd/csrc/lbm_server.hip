@@ -298,10 +298,14 @@ void retire(lbm_server *s, Request &r, bool check_only) {
         hipStreamSynchronize(s->stream) != hipSuccess)
         hc = LBM_ERR_HIP;
     if (hc != LBM_OK || range) {
-        std::string msg = range ? std::string("16-bit encode saturated")
-                          : hc == LBM_ERR_DIVERGED ? "diverged: " + std::to_string(counts[0]) + " non-finite sites, " +
-                                                         std::to_string(counts[1]) + " sites with rho <= 0"
-                                                   : std::string("health check: ") + lbm_last_error();
+        // A binary16 code past its largest finite value means a deviation grew 1024-fold beyond
+        // the largest initial one, which in practice is a diverging run; a bfloat16 code is
+        // flagged only when the value itself is no longer finite.
+        const std::string sites = std::to_string(counts[0]) + " non-finite sites, " +
+                                  std::to_string(counts[1]) + " sites with rho <= 0";
+        std::string msg = range && s->prm.storage == LBM_F16DEV ? "16-bit encode saturated (diverging or out of range): " + sites
+                          : range || hc == LBM_ERR_DIVERGED     ? "diverged: " + sites
+                                                                : std::string("health check: ") + lbm_last_error();
         lbm_destroy(r.lat);
         r.lat = nullptr;
         std::lock_guard<std::mutex> lk(s->mu);

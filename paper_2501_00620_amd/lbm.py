@@ -263,6 +263,19 @@ def lattice_bytes(nx, ny, nz, storage="f32", mode="thermal"):
     return int(lib.lbm_lattice_bytes(C.byref(p)))
 
 
+def codec_reference(rho, T, rho_ref=None, T_ref=None):
+    """(rho_ref, T_ref) of a lattice's deviation codec: the given values, else the mean density
+    and mean temperature of the initial fields (else 1 and 1/3 when those are not usable; the
+    fields themselves are then rejected where they are set)."""
+    if rho_ref is None:
+        m = float(np.mean(rho))
+        rho_ref = m if np.isfinite(m) and m > 0 else 1.0
+    if T_ref is None:
+        m = float(np.mean(T))
+        T_ref = m if np.isfinite(m) else 1.0 / 3.0
+    return rho_ref, T_ref
+
+
 class Server:
     """Continuous batching of many independent lattices (see include/lbm.h, lbm_server_*).
 
@@ -299,11 +312,15 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
-    def submit(self, rho, u, T, tau, steps, mode="thermal", T_ref=1.0 / 3.0, rho_ref=1.0):
+    def submit(self, rho, u, T, tau, steps, mode="thermal", T_ref=None, rho_ref=None):
+        """Queue one simulation (host arrays, copied).  The deviation codec's reference
+        equilibrium defaults to the request's mean density (a conserved quantity) and mean
+        temperature, which keeps stored deviations small where the density varies widely."""
         rho = np.ascontiguousarray(rho, dtype=np.float64)
         nz, ny, nx = rho.shape
         u = np.ascontiguousarray(np.broadcast_to(u, (3, nz, ny, nx)), dtype=np.float64)
         T = np.ascontiguousarray(np.broadcast_to(T, (nz, ny, nx)), dtype=np.float64)
+        rho_ref, T_ref = codec_reference(rho, T, rho_ref, T_ref)
         p = lbm_params(nx, ny, nz, float(tau), float(T_ref), float(rho_ref), STORAGE[self.storage], MODE[mode])
         rid = C.c_long()
         _check(_lib.lbm_server_submit(self._h, C.byref(p), rho.ctypes.data_as(C.c_void_p),

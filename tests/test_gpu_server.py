@@ -27,7 +27,8 @@ def lbm():
 def alone(fields, tau, steps, storage, mode="thermal"):
     rho, u, T = fields
     nz, ny, nx = rho.shape
-    g = lbm().Lattice(nx, ny, nz, tau, storage=storage, mode=mode, kernel="fused")
+    rho_ref, T_ref = lbm().codec_reference(rho, T)  # the server's default reference
+    g = lbm().Lattice(nx, ny, nz, tau, storage=storage, mode=mode, kernel="fused", rho_ref=rho_ref, T_ref=T_ref)
     g.set_fields(rho, u, T)
     g.step(steps)
     r, uu, TT = g.moments()
