@@ -26,6 +26,12 @@
 
 namespace lbm {
 
+#ifndef FUSED_RING_EARLY
+#define FUSED_RING_EARLY 0  // ring populations issued before the tile's sources are evaluated
+#endif
+#ifndef FUSED_PREFETCH_RING
+#define FUSED_PREFETCH_RING 0  // ring populations loaded one plane ahead too (more VGPRs)
+#endif
 #ifndef GRAD_GROUP
 #define GRAD_GROUP 3    // neighbours per scheduling group in the gradient
 #endif
@@ -33,8 +39,8 @@ namespace lbm {
 #define GATHER_GROUP 5  // directions per scheduling group in the gather
 #endif
 
-template <int TY_> struct Tile {
-    static constexpr int TX = 64, TY = TY_;
+template <int TX_, int TY_> struct Tile {
+    static constexpr int TX = TX_, TY = TY_;
     static constexpr int NT = TX * TY;            // threads = tile sites
     static constexpr int HX = TX + 2, HY = TY + 2;
     static constexpr int NS = HX * HY;            // source sites per LDS plane (tile + ring)
@@ -45,8 +51,14 @@ template <int TY_> struct Tile {
 
 // 4- and 2-byte storage compute in float: 64 x 8 tiles (71 KB of sources + 59 KB of staged
 // bbar*); double needs twice the bytes, so 64 x 2.
-template <int S> struct TileFor { using type = Tile<8>; };
-template <> struct TileFor<0> { using type = Tile<2>; };
+#ifndef FUSED_TX
+#define FUSED_TX 64
+#endif
+#ifndef FUSED_TY
+#define FUSED_TY 8
+#endif
+template <int S> struct TileFor { using type = Tile<FUSED_TX, FUSED_TY>; };
+template <> struct TileFor<0> { using type = Tile<64, 2>; };
 
 struct FusedGeo {
     int tiles_x, tiles_y, nchunks, zchunk;
@@ -82,22 +94,35 @@ template <int S> struct Buf {
                                                      0x00020000);
         }
     }
-    // plane K of this array holds codec field F0 + K.  The plane's byte offset in its group goes
-    // to the scalar-offset operand through readfirstlane, so it is known to be wave-uniform.
-    template <int K, int F0> __device__ __forceinline__ C loadf(int off, const Codec &cd) const {
+    // A value as loaded (the storage type), decoded only where it is used: a load whose result
+    // is kept raw can be issued one plane ahead without the wait for it coming at the load.
+    using R = T;
+    // plane K of this array: its byte offset in its group goes to the scalar-offset operand
+    // through readfirstlane, so it is known to be wave-uniform.
+    template <int K> __device__ __forceinline__ R loadraw(int off) const {
         constexpr int g = K / PPG, j = K % PPG;
         const __amdgpu_buffer_rsrc_t rs = r[g];
         const int so = __builtin_amdgcn_readfirstlane(j * pb);
         if constexpr (S == 0) {
-            auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, so, 0);
-            return __builtin_bit_cast(double, v);
+            return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, so, 0));
         } else if constexpr (S == 1) {
             return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, so, 0));
-        } else if constexpr (S == 2) {
-            return cd.scale[F0 + K] * half_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, so, 0));
-        } else {  // bf16 codes hold the deviation itself (unit scale)
-            return bf16_bits_to_float(__builtin_amdgcn_raw_buffer_load_b16(rs, off, so, 0));
+        } else {
+            return __builtin_amdgcn_raw_buffer_load_b16(rs, off, so, 0);
         }
+    }
+    // plane K of this array holds codec field F0 + K
+    template <int K, int F0> __device__ __forceinline__ C decode(R v, const Codec &cd) const {
+        if constexpr (S == 0 || S == 1) {
+            return v;
+        } else if constexpr (S == 2) {
+            return cd.scale[F0 + K] * half_bits_to_float(v);
+        } else {  // bf16 codes hold the deviation itself (unit scale)
+            return bf16_bits_to_float(v);
+        }
+    }
+    template <int K, int F0> __device__ __forceinline__ C loadf(int off, const Codec &cd) const {
+        return decode<K, F0>(loadraw<K>(off), cd);
     }
     // Stores a value; for 16-bit codes, amax collects |code| so that one comparison after the
     // sweep detects overflow (an overflowing code is stored as +-inf and reported as RANGE).
@@ -168,8 +193,10 @@ __device__ __forceinline__ void source_site_gathered(const Buf<S> &bF, const Buf
 
 // Sources of one site whose bbar* neighbourhood is staged in LDS: the gather of Eq. 66 reads
 // the staged planes bs[0..2] (planes z-1, z, z+1); bidx is the site's staging index.
+// The site's populations arrive raw (loaded one plane ahead).
 template <int S, typename TL, bool KEEP>
-__device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typename Storage<S>::C *__restrict__ Tf,
+__device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typename Buf<S>::R raw[Q],
+                                                   const typename Storage<S>::C *__restrict__ Tf,
                                                    typename Storage<S>::C Tconst,
                                                    const StepConst<typename Storage<S>::C> &k, const Codec &cd,
                                                    int s, int bidx, const typename Storage<S>::C *const bs[3],
@@ -177,7 +204,7 @@ __device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typen
                                                    SiteState<typename Storage<S>::C> &keep) {
     using C = typename Storage<S>::C;
     C d[Q], beta[NB];
-    load_pops<S>(bF, s * (int)sizeof(typename Storage<S>::T), cd, d);
+    Unroll<0, Q>::run([&](auto I) { d[I] = bF.template decode<I, 0>(raw[I], cd); });
     const PopMoments<C> m = pop_moments(d, k.rho_ref);
     C acc[NB];
 #pragma unroll
@@ -289,8 +316,47 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
 
     const bool thin = g.nz <= 2;
 
-    auto stage = [&](int q, int slot) {
+    // Raw values loaded one plane ahead: the staged bbar* of the next plane to stage, and the
+    // populations of the next plane whose sources are evaluated (tile site and ring sites).
+    // Loads one plane ahead (PIPE) for 4- and 2-byte storage; the double-precision kernel, at
+    // one wave per SIMD already, has no registers to hold them and loads where it uses.
+    constexpr bool PIPE = !GATHERED && S != 0;
+    using R = typename Buf<S>::R;
+    R sraw[NSTAGE][NB];
+    R praw[Q];
+    R rraw[NRING][Q];
+    (void)sraw;
+    (void)praw;
+    (void)rraw;
+
+    auto stage_issue = [&](int q) {
         if constexpr (!GATHERED) {
+            const int zo = wrapc(q, g.nz) * nxy;
+#pragma unroll
+            for (int j = 0; j < NSTAGE; j++) {
+                if (threadIdx.x + j * TL::NT < NB2) {
+                    const int off = (zo + sxy[j]) * SB;
+                    Unroll<0, NB>::run([&](auto c) { sraw[j][c] = bB.template loadraw<c>(off); });
+                }
+            }
+        }
+    };
+    auto stage_commit = [&](int slot) {
+        if constexpr (!GATHERED) {
+#pragma unroll
+            for (int j = 0; j < NSTAGE; j++) {
+                const int r = threadIdx.x + j * TL::NT;
+                if (r < NB2) {
+                    Unroll<0, NB>::run([&](auto c) { bst[slot][c * NB2 + r] = bB.template decode<c, Q>(sraw[j][c], cd); });
+                }
+            }
+        }
+    };
+    auto stage = [&](int q, int slot) {
+        if constexpr (PIPE) {
+            stage_issue(q);
+            stage_commit(slot);
+        } else if constexpr (!GATHERED) {
             const int zo = wrapc(q, g.nz) * nxy;
 #pragma unroll
             for (int j = 0; j < NSTAGE; j++) {
@@ -305,8 +371,29 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
     // slot of a staged plane q: (q - z0 + 6) % 3 when marching, q itself when nz <= 2
     auto bslot = [&](int q) { return thin ? wrapc(q, g.nz) : (q - z0 + 6) % 3; };
 
-    // sources of plane p into LDS source slot `slot`, keeping the tile state
-    auto fill = [&](int p, int slot, SiteState<C> &keep) {
+    // populations of plane p (tile site and ring sites), kept raw
+    auto fill_issue = [&](int p) {
+        if constexpr (!GATHERED) {
+            // (with PIPE, this runs one plane ahead of fill_compute)
+            const int zo = wrapc(p, g.nz) * nxy;
+            const int off = (zo + ixy) * SB;
+            Unroll<0, Q>::run([&](auto I) { praw[I] = bF.template loadraw<I>(off); });
+#if FUSED_PREFETCH_RING
+            if constexpr (PIPE)
+#pragma unroll
+            for (int j = 0; j < NRING; j++) {
+                if (threadIdx.x + j * TL::NT < TL::NH) {
+                    const int roff = (zo + rxy[j]) * SB;
+                    Unroll<0, Q>::run([&](auto I) { rraw[j][I] = bF.template loadraw<I>(roff); });
+                }
+            }
+#endif
+        }
+    };
+    // sources of plane p into LDS source slot `slot`, keeping the tile state; the staged path
+    // takes the populations fill_issue(p) loaded
+    // (b0, b1, b2: staging slots of planes p-1, p, p+1)
+    auto fill_compute = [&](int p, int slot, SiteState<C> &keep, int b0, int b1, int b2) {
         const int zo = wrapc(p, g.nz) * nxy;
         if constexpr (GATHERED) {
             source_site_gathered<S, NS, true>(bF, bB, Tf, Tconst, k, cd, zo + ixy, lds[slot], iidx, keep);
@@ -319,18 +406,40 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
                 }
             }
         } else {
-            const C *bs[3] = {bst[bslot(p - 1)], bst[bslot(p)], bst[bslot(p + 1)]};
-            source_site_staged<S, TL, true>(bF, Tf, Tconst, k, cd, zo + ixy, ibidx, bs, lds[slot], iidx, keep);
+            const C *bs[3] = {bst[b0], bst[b1], bst[b2]};
+            auto ring_loads = [&]() {
+#pragma unroll
+                for (int j = 0; j < NRING; j++) {
+                    if (threadIdx.x + j * TL::NT < TL::NH) {
+                        const int roff = (zo + rxy[j]) * SB;
+                        Unroll<0, Q>::run([&](auto I) { rraw[j][I] = bF.template loadraw<I>(roff); });
+                    }
+                }
+            };
+            // ring populations not loaded one plane ahead: issued before the tile's own sources
+            // (whose evaluation covers part of their latency) or just before their use
+            constexpr bool ahead = PIPE && FUSED_PREFETCH_RING;
+            constexpr bool early = PIPE && !FUSED_PREFETCH_RING && FUSED_RING_EARLY;
+            if constexpr (early) ring_loads();
+            source_site_staged<S, TL, true>(bF, praw, Tf, Tconst, k, cd, zo + ixy, ibidx, bs, lds[slot], iidx, keep);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < NRING; j++) {
                 if (threadIdx.x + j * TL::NT < TL::NH) {
+                    if constexpr (!ahead && !early) {
+                        const int roff = (zo + rxy[j]) * SB;
+                        Unroll<0, Q>::run([&](auto I) { rraw[j][I] = bF.template loadraw<I>(roff); });
+                    }
                     SiteState<C> dummy;
-                    source_site_staged<S, TL, false>(bF, Tf, Tconst, k, cd, zo + rxy[j], rbidx[j], bs, lds[slot],
-                                                     rlidx[j], dummy);
+                    source_site_staged<S, TL, false>(bF, rraw[j], Tf, Tconst, k, cd, zo + rxy[j], rbidx[j], bs,
+                                                     lds[slot], rlidx[j], dummy);
                 }
             }
         }
+    };
+    auto fill = [&](int p, int slot, SiteState<C> &keep) {
+        fill_issue(p);
+        fill_compute(p, slot, keep, bslot(p - 1), bslot(p), bslot(p + 1));
     };
 
     // gradient, collision and push of plane z from the source slots (sm, s0, sp)
@@ -389,17 +498,38 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
         stage(z0 + 1, bslot(z0 + 1));  // overwrites the slot of z0 - 2
         __syncthreads();
         fill(z0, 0, sa);
+        if constexpr (PIPE) {  // the loads the first iteration consumes
+            stage_issue(z0 + 2);
+            fill_issue(z0 + 1);
+        }
         __syncthreads();
-        // one plane: stage z+2, sources of z+1 into `nxt`, then the final of z from `cur`
+        // one plane: stage z+2, sources of z+1 into `nxt`, then the final of z from `cur`; the
+        // global loads of the staging and the sources are issued one iteration ahead.  Plane q's
+        // staging slot and source slot are both (q - z0) mod 3.
         auto iter = [&](int z, SiteState<C> &cur, SiteState<C> &nxt) {
-            stage(z + 2, bslot(z + 2));  // slot of plane z-1, whose last gather was for plane z
+            const int m = (z - z0) % 3, m1 = (m + 1) % 3, m2 = (m + 2) % 3;
+            const bool more = z + 1 < z1;
+            // the staged slot is that of plane z-1, whose last gather was for plane z
+            if constexpr (PIPE) {
+                stage_commit(m2);
+                if (more) stage_issue(z + 3);
+            } else {
+                stage(z + 2, m2);
+            }
             __syncthreads();
-            fill(z + 1, (z + 1 - z0 + 3) % 3, nxt);
+            if constexpr (PIPE) {
+                fill_compute(z + 1, m1, nxt, m, m1, m2);
+                if (more) fill_issue(z + 2);
+            } else {
+                fill_issue(z + 1);
+                fill_compute(z + 1, m1, nxt, m, m1, m2);
+            }
             __syncthreads();
-            final_plane(z, (z - 1 - z0 + 3) % 3, (z - z0) % 3, (z + 1 - z0) % 3, cur);
-            // the next staging overwrites the bbar* plane read by this plane's gathers, and the
-            // next fill the source plane read by this plane's gradients
-            __syncthreads();
+            final_plane(z, m2, m, m1, cur);
+            // No barrier here: the next staging overwrites the bbar* slot of plane z, last read
+            // by this iteration's fill (before the barrier above), and the next fill overwrites
+            // the source slot of plane z-1, last read by this final, which the next iteration's
+            // first barrier separates from it.
         };
         for (int z = z0; z < z1; z++) {
             iter(z, sa, sb);
@@ -457,7 +587,10 @@ template <int S> inline FusedGeo fused_geometry(const Geo &g) {
         return fg;
     }
     // enough work-groups to fill the 256 CUs several times over, chunks of at least 16 planes
-    int want = (1024 + tiles - 1) / tiles;
+#ifndef FUSED_WANT_WG
+#define FUSED_WANT_WG 1024
+#endif
+    int want = (FUSED_WANT_WG + tiles - 1) / tiles;
     int maxc = g.nz / 16 > 0 ? g.nz / 16 : 1;
     int nch = want < maxc ? want : maxc;
     if (nch < 1) nch = 1;
