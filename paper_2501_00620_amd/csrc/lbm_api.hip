@@ -183,7 +183,7 @@ template <int S> int step_fused(lbm_lattice *h) {
     const StepConst<C> k = step_const<C>(h);
     int rc = launch_fused<S>((const T *)h->F[h->cur], (const T *)h->B[h->cur], (T *)h->F[1 - h->cur],
                              (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->flag,
-                             h->gathered, h->stream);
+                             h->gathered, h->slots, h->stream);
     if (rc) return fail(LBM_ERR_HIP, "fused launch failed");
     rc = check_launch();
     if (rc) return rc;
@@ -232,6 +232,10 @@ int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out) {
         (void)hipGetLastError();
         return fail(e == hipErrorOutOfMemory ? LBM_ERR_OOM : LBM_ERR_HIP, "allocation: %s", hipGetErrorString(e));
     }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        h->slots = cus;
     codec_defaults(h);
     *out = h;
     return LBM_OK;

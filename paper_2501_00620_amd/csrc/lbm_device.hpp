@@ -194,6 +194,11 @@ __device__ __forceinline__ void variance_eq_dev(C ux, C uy, C uz, C theta, C b[N
     b[5] = uy * uz * third;
 }
 
+// 1/x: the hardware reciprocal in single precision (within about 1 ulp; the single-precision
+// path is held to a relative error of 1e-5), correctly rounded division in double.
+template <typename C> __device__ __forceinline__ C recip(C x) { return C(1) / x; }
+template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Moments of the deviation populations.
 template <typename C> struct PopMoments {
     C drho, rho, jx, jy, jz, P;
@@ -219,7 +224,7 @@ __device__ __forceinline__ PopMoments<C> pop_moments(const C d[Q], C rho_ref) {
 template <typename C>
 __device__ __forceinline__ void predictor_sources(const PopMoments<C> &m, const C beta[NB], C theta_iso,
                                                   const StepConst<C> &k, C src[NSRC]) {
-    const C inv = C(1) / m.rho;
+    const C inv = recip(m.rho);
     const C ux = m.jx * inv, uy = m.jy * inv, uz = m.jz * inv;
     const C u2 = ux * ux + uy * uy + uz * uz;
     const C trb = beta[0] + beta[1] + beta[2];
@@ -313,7 +318,7 @@ template <typename C>
 __device__ __forceinline__ void collide(C d[Q], C beta[NB], const PopMoments<C> &m, const C F[3],
                                         const C S[6], C theta_iso, const StepConst<C> &k, C *out_u = nullptr,
                                         C *out_theta = nullptr) {
-    const C inv = C(1) / m.rho;
+    const C inv = recip(m.rho);
     const C ux = (m.jx + C(0.5) * F[0]) * inv;  // Eq. 57
     const C uy = (m.jy + C(0.5) * F[1]) * inv;
     const C uz = (m.jz + C(0.5) * F[2]) * inv;

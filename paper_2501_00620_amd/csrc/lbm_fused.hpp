@@ -26,9 +26,6 @@
 
 namespace lbm {
 
-#ifndef FUSED_RING_EARLY
-#define FUSED_RING_EARLY 0  // ring populations issued before the tile's sources are evaluated
-#endif
 #ifndef FUSED_PREFETCH_RING
 #define FUSED_PREFETCH_RING 0  // ring populations loaded one plane ahead too (more VGPRs)
 #endif
@@ -218,7 +215,7 @@ __device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typen
         for (int c = 0; c < NB; c++) acc[c] = fma(wgt, pl[c * TL::NB2 + off], acc[c]);
         if constexpr (I % GATHER_GROUP == GATHER_GROUP - 1) __builtin_amdgcn_sched_barrier(0);
     });
-    const C inv = C(1) / m.rho;
+    const C inv = recip(m.rho);
 #pragma unroll
     for (int c = 0; c < NB; c++) beta[c] = acc[c] * inv;
     const C th = site_T(Tf, Tconst, s);
@@ -407,26 +404,15 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
             }
         } else {
             const C *bs[3] = {bst[b0], bst[b1], bst[b2]};
-            auto ring_loads = [&]() {
-#pragma unroll
-                for (int j = 0; j < NRING; j++) {
-                    if (threadIdx.x + j * TL::NT < TL::NH) {
-                        const int roff = (zo + rxy[j]) * SB;
-                        Unroll<0, Q>::run([&](auto I) { rraw[j][I] = bF.template loadraw<I>(roff); });
-                    }
-                }
-            };
-            // ring populations not loaded one plane ahead: issued before the tile's own sources
-            // (whose evaluation covers part of their latency) or just before their use
+            // ring populations not loaded one plane ahead are loaded just before their use
+            // (issued before the tile's own sources, they cost more registers than they save)
             constexpr bool ahead = PIPE && FUSED_PREFETCH_RING;
-            constexpr bool early = PIPE && !FUSED_PREFETCH_RING && FUSED_RING_EARLY;
-            if constexpr (early) ring_loads();
             source_site_staged<S, TL, true>(bF, praw, Tf, Tconst, k, cd, zo + ixy, ibidx, bs, lds[slot], iidx, keep);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < NRING; j++) {
                 if (threadIdx.x + j * TL::NT < TL::NH) {
-                    if constexpr (!ahead && !early) {
+                    if constexpr (!ahead) {
                         const int roff = (zo + rxy[j]) * SB;
                         Unroll<0, Q>::run([&](auto I) { rraw[j][I] = bF.template loadraw<I>(roff); });
                     }
@@ -575,26 +561,37 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
     report_range<S>(amax, flag);
 }
 
-template <int S> inline FusedGeo fused_geometry(const Geo &g) {
+// Tiles of the xy plane times z chunks.  `slots` is the number of work-groups resident at once
+// (one per CU: each takes more than half of a CU's LDS).  A chunk costs its planes plus about
+// two of warm-up, and the work-groups run in ceil(blocks / slots) rounds, so the chunk count
+// minimises rounds x (chunk + 2): one round with all CUs marching in step through their chunk
+// is best (neighbouring tiles then share their halo rings in L2 at the same time).  Chunks keep
+// at least 16 planes.
+template <int S> inline FusedGeo fused_geometry(const Geo &g, int slots) {
     using TL = typename TileFor<S>::type;
     FusedGeo fg;
     fg.tiles_x = (g.nx + TL::TX - 1) / TL::TX;
     fg.tiles_y = (g.ny + TL::TY - 1) / TL::TY;
-    const int tiles = fg.tiles_x * fg.tiles_y;
+    const long long tiles = (long long)fg.tiles_x * fg.tiles_y;
     if (g.nz <= 2) {
         fg.nchunks = 1;
         fg.zchunk = g.nz;
         return fg;
     }
-    // enough work-groups to fill the 256 CUs several times over, chunks of at least 16 planes
-#ifndef FUSED_WANT_WG
-#define FUSED_WANT_WG 1024
-#endif
-    int want = (FUSED_WANT_WG + tiles - 1) / tiles;
-    int maxc = g.nz / 16 > 0 ? g.nz / 16 : 1;
-    int nch = want < maxc ? want : maxc;
-    if (nch < 1) nch = 1;
-    fg.zchunk = (g.nz + nch - 1) / nch;
+    if (slots < 1) slots = 1;
+    const int maxc = g.nz / 16 > 0 ? g.nz / 16 : 1;
+    int best = 1;
+    long long best_cost = -1;
+    for (int nch = 1; nch <= maxc; nch++) {
+        const long long zc = (g.nz + nch - 1) / nch;
+        const long long rounds = (tiles * nch + slots - 1) / slots;
+        const long long cost = rounds * (zc + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = nch;
+        }
+    }
+    fg.zchunk = (g.nz + best - 1) / best;
     fg.nchunks = (g.nz + fg.zchunk - 1) / fg.zchunk;
     return fg;
 }
@@ -611,9 +608,9 @@ template <int S>
 int launch_fused(const typename Storage<S>::T *F, const typename Storage<S>::T *B, typename Storage<S>::T *Fo,
                  typename Storage<S>::T *Bo, const typename Storage<S>::C *Tf, typename Storage<S>::C Tconst,
                  const Geo &g, const StepConst<typename Storage<S>::C> &k, const Codec &cd, unsigned *flag,
-                 bool gathered, hipStream_t stream) {
+                 bool gathered, int slots, hipStream_t stream) {
     using TL = typename TileFor<S>::type;
-    const FusedGeo fg = fused_geometry<S>(g);
+    const FusedGeo fg = fused_geometry<S>(g, slots);
     const long long blocks = (long long)fg.tiles_x * fg.tiles_y * fg.nchunks;
     if (blocks > 2147483647LL) return -1;
     const dim3 grid((unsigned)blocks), block(TL::NT);

@@ -25,6 +25,7 @@ struct lbm_lattice {
     double *red_out = nullptr;  // RED_K
     unsigned *flag = nullptr;   // saturation flag
     int kernel = 0;
+    int slots = 256;            // fused work-groups resident at once (one per CU)
 };
 
 namespace lbm {

@@ -60,7 +60,7 @@ __device__ __forceinline__ void load_site(const typename Storage<S>::T *__restri
 #pragma unroll
             for (int c = 0; c < NB; c++) acc[c] += wgt * Storage<S>::load(B, (size_t)c * n + up, Q + c, cd);
         });
-        const C inv = C(1) / m.rho;
+        const C inv = recip(m.rho);
 #pragma unroll
         for (int c = 0; c < NB; c++) bbar[c] = acc[c] * inv;
     }

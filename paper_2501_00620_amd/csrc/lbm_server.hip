@@ -221,7 +221,7 @@ int upload_tables(lbm_server *s) {
         d.steps_left = (int)std::min<long>(r.steps_left, s->prm.bundle_steps);
         d.g = Geo{h->p.nx, h->p.ny, h->p.nz, h->n};
         dispatch_serve(s->prm.storage, [&](auto SI) -> int {
-            d.fg = fused_geometry<decltype(SI)::value>(d.g);
+            d.fg = fused_geometry<decltype(SI)::value>(d.g, s->grid);
             return 0;
         });
         const double omega = 1.0 / (h->p.tau + 0.5);
