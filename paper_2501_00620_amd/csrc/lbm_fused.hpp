@@ -56,6 +56,15 @@ template <int TX_, int TY_> struct Tile {
 #endif
 template <int S> struct TileFor { using type = Tile<FUSED_TX, FUSED_TY>; };
 template <> struct TileFor<0> { using type = Tile<64, 2>; };
+// Tiles of the one-plane serving kernel: it has LDS to spare, and 256-thread work-groups let
+// two of them share a CU at the same register budget, each covering the other's load waits.
+#ifndef SERVE_THIN_TX
+#define SERVE_THIN_TX 64
+#endif
+#ifndef SERVE_THIN_TY
+#define SERVE_THIN_TY 4
+#endif
+template <int S> struct ThinTileFor { using type = Tile<SERVE_THIN_TX, SERVE_THIN_TY>; };
 
 struct FusedGeo {
     int tiles_x, tiles_y, nchunks, zchunk;
@@ -232,8 +241,10 @@ __device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typen
 
 // One work-group sweeps tile (tx, ty) of z chunk `chunk` for one step.  Shared by the
 // single-lattice kernel and the multi-lattice serving kernel.  HASK: T_ref != 1/3 (the constant
-// part of rho b enters the second-moment source).  amax collects |16-bit codes| stored.
-template <int S, bool GATHERED, bool HASK>
+// part of rho b enters the second-moment source).  THIN1: the lattice has exactly one z plane
+// (one LDS slot of each kind, about a third of the LDS, so that several work-groups share a CU).
+// amax collects |16-bit codes| stored.
+template <int S, bool GATHERED, bool HASK, bool THIN1 = false, typename TL = typename TileFor<S>::type>
 __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restrict__ F,
                                            const typename Storage<S>::T *__restrict__ B,
                                            typename Storage<S>::T *__restrict__ Fo,
@@ -244,12 +255,12 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
                                            const FusedGeo &fg, int tx, int ty, int chunk, float &amax) {
     using C = typename Storage<S>::C;
     using T = typename Storage<S>::T;
-    using TL = typename TileFor<S>::type;
     constexpr int TX = TL::TX, TY = TL::TY, NS = TL::NS, NB2 = TL::NB2;
     constexpr int NSTAGE = (NB2 + TL::NT - 1) / TL::NT;  // staging sites per thread
     constexpr int SB = (int)sizeof(T);
-    __shared__ C lds[3][NSRC * NS];
-    __shared__ C bst[GATHERED ? 1 : 3][GATHERED ? 1 : NB * NB2];
+    constexpr int NSLOT = THIN1 ? 1 : 3;
+    __shared__ C lds[NSLOT][NSRC * NS];
+    __shared__ C bst[GATHERED ? 1 : NSLOT][GATHERED ? 1 : NB * NB2];
 
     Buf<S> bF, bB, bFo, bBo;
     bF.init(F, Q, g.n);
@@ -311,13 +322,13 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
         sxy[j] = wrapc(y0 + by, g.ny) * g.nx + wrapc(x0 + bx, g.nx);
     }
 
-    const bool thin = g.nz <= 2;
+    const bool thin = THIN1 || g.nz <= 2;
 
     // Raw values loaded one plane ahead: the staged bbar* of the next plane to stage, and the
     // populations of the next plane whose sources are evaluated (tile site and ring sites).
     // Loads one plane ahead (PIPE) for 4- and 2-byte storage; the double-precision kernel, at
     // one wave per SIMD already, has no registers to hold them and loads where it uses.
-    constexpr bool PIPE = !GATHERED && S != 0;
+    constexpr bool PIPE = !GATHERED && S != 0 && !THIN1;
     using R = typename Buf<S>::R;
     R sraw[NSTAGE][NB];
     R praw[Q];
@@ -466,7 +477,13 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
     };
 
     SiteState<C> sa, sb;
-    if (thin) {
+    if constexpr (THIN1) {
+        stage(0, 0);
+        __syncthreads();
+        fill(0, 0, sa);
+        __syncthreads();
+        final_plane(0, 0, 0, 0, sa);
+    } else if (thin) {
         for (int q = 0; q < g.nz; q++) stage(q, q);
         __syncthreads();
         fill(0, 0, sa);
@@ -567,8 +584,7 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
 // minimises rounds x (chunk + 2): one round with all CUs marching in step through their chunk
 // is best (neighbouring tiles then share their halo rings in L2 at the same time).  Chunks keep
 // at least 16 planes.
-template <int S> inline FusedGeo fused_geometry(const Geo &g, int slots) {
-    using TL = typename TileFor<S>::type;
+template <typename TL> inline FusedGeo fused_geometry_t(const Geo &g, int slots) {
     FusedGeo fg;
     fg.tiles_x = (g.nx + TL::TX - 1) / TL::TX;
     fg.tiles_y = (g.ny + TL::TY - 1) / TL::TY;
@@ -594,6 +610,10 @@ template <int S> inline FusedGeo fused_geometry(const Geo &g, int slots) {
     fg.zchunk = (g.nz + best - 1) / best;
     fg.nchunks = (g.nz + fg.zchunk - 1) / fg.zchunk;
     return fg;
+}
+
+template <int S> inline FusedGeo fused_geometry(const Geo &g, int slots) {
+    return fused_geometry_t<typename TileFor<S>::type>(g, slots);
 }
 
 // Every buffer-resource group (PPG planes) must stay below 4 GiB.

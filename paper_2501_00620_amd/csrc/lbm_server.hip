@@ -52,13 +52,23 @@ struct TileRef {
     int tile;  // (chunk * tiles_y + ty) * tiles_x + tx
 };
 
-template <int S>
-__global__ void __launch_bounds__(TileFor<S>::type::NT) __attribute__((amdgpu_waves_per_eu(FUSED_WAVES_PER_EU)))
+#ifndef SERVE_THIN_WAVES_PER_EU
+#define SERVE_THIN_WAVES_PER_EU 2
+#endif
+template <int S, bool THIN1>
+using ServeTile = typename std::conditional<THIN1, typename ThinTileFor<S>::type, typename TileFor<S>::type>::type;
+
+template <int S, bool THIN1>
+__global__ void __launch_bounds__((ServeTile<S, THIN1>::NT))
+    __attribute__((amdgpu_waves_per_eu(THIN1 ? SERVE_THIN_WAVES_PER_EU : FUSED_WAVES_PER_EU)))
 k_serve(const ServeDesc *__restrict__ descs, const TileRef *__restrict__ tiles, const int *__restrict__ ntiles,
         int step) {
     using T = typename Storage<S>::T;
-    const int nt = *ntiles;
-    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    // the table lists the tiles of one-plane lattices first: [0, ntiles[0]) for THIN1, then
+    // [ntiles[0], ntiles[1]) for the rest
+    const int lo = THIN1 ? 0 : ntiles[0];
+    const int hi = THIN1 ? ntiles[0] : ntiles[1];
+    for (int t = lo + (int)blockIdx.x; t < hi; t += (int)gridDim.x) {
         const TileRef e = tiles[t];
         const ServeDesc &d = descs[e.lat];
         if (step >= d.steps_left) continue;  // this lattice is done for the bundle
@@ -69,7 +79,7 @@ k_serve(const ServeDesc *__restrict__ descs, const TileRef *__restrict__ tiles, 
         const int ty = L % d.fg.tiles_y;
         const int chunk = L / d.fg.tiles_y;
         float amax = 0.0f;
-        sweep_tile<S, false, true>((const T *)d.F[cur], (const T *)d.B[cur], (T *)d.F[1 - cur], (T *)d.B[1 - cur],
+        sweep_tile<S, false, true, THIN1, ServeTile<S, THIN1>>((const T *)d.F[cur], (const T *)d.B[cur], (T *)d.F[1 - cur], (T *)d.B[1 - cur],
                                    d.Tf, d.Tconst, d.g, d.k, d.cd, d.fg, tx, ty, chunk, amax);
         report_range<S>(amax, d.flag);
     }
@@ -99,7 +109,8 @@ struct lbm_server {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int device = 0;
-    int grid = 0;  // persistent work-groups
+    int grid = 0;       // persistent work-groups of the general kernel
+    int grid_thin = 0;  // persistent work-groups of the one-plane kernel
 
     std::mutex mu;
     std::condition_variable cv;       // worker wake-up
@@ -120,6 +131,8 @@ struct lbm_server {
     std::vector<ServeDesc> h_desc;
     std::vector<TileRef> h_tiles;
     bool tables_dirty = true;
+    int n_thin = 0, n_all = 0;                // tile counts of the current table
+    bool graph_thin = false, graph_gen = false;  // kernels the captured bundle launches
     hipGraphExec_t graph = nullptr;
 
     // counters
@@ -221,7 +234,9 @@ int upload_tables(lbm_server *s) {
         d.steps_left = (int)std::min<long>(r.steps_left, s->prm.bundle_steps);
         d.g = Geo{h->p.nx, h->p.ny, h->p.nz, h->n};
         dispatch_serve(s->prm.storage, [&](auto SI) -> int {
-            d.fg = fused_geometry<decltype(SI)::value>(d.g, s->grid);
+            constexpr int S = decltype(SI)::value;
+            d.fg = d.g.nz == 1 ? fused_geometry_t<ServeTile<S, true>>(d.g, s->grid_thin)
+                               : fused_geometry_t<ServeTile<S, false>>(d.g, s->grid);
             return 0;
         });
         const double omega = 1.0 / (h->p.tau + 0.5);
@@ -236,13 +251,20 @@ int upload_tables(lbm_server *s) {
         d.flag = h->flag;
         d.cd = h->codec;
         s->h_desc.push_back(d);
-        if (s->tables_dirty) {
-            const int nt = d.fg.tiles_x * d.fg.tiles_y * d.fg.nchunks;
-            for (int t = 0; t < nt; t++) s->h_tiles.push_back(TileRef{(int)a, t});
-        }
     }
     if (s->tables_dirty) {
-        const int nt = (int)s->h_tiles.size();
+        // tiles of one-plane lattices first (the one-plane kernel), then the others
+        for (int pass = 0; pass < 2; pass++) {
+            for (size_t a = 0; a < s->h_desc.size(); a++) {
+                const ServeDesc &d = s->h_desc[a];
+                if ((d.g.nz == 1) != (pass == 0)) continue;
+                const int nt = d.fg.tiles_x * d.fg.tiles_y * d.fg.nchunks;
+                for (int t = 0; t < nt; t++) s->h_tiles.push_back(TileRef{(int)a, t});
+            }
+            if (pass == 0) s->n_thin = (int)s->h_tiles.size();
+        }
+        s->n_all = (int)s->h_tiles.size();
+        const int nt = s->n_all;
         if (nt > s->tile_cap) {
             if (s->graph) {
                 (void)hipGraphExecDestroy(s->graph);
@@ -254,9 +276,17 @@ int upload_tables(lbm_server *s) {
         }
         if (nt && hipMemcpyAsync(s->d_tiles, s->h_tiles.data(), sizeof(TileRef) * nt, hipMemcpyHostToDevice, s->stream) != hipSuccess)
             return LBM_ERR_HIP;
-        if (hipMemcpyAsync(s->d_ntiles, &nt, sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess) return LBM_ERR_HIP;
-        // the copy of nt reads a stack value: make it complete before it goes out of scope
+        const int counts[2] = {s->n_thin, s->n_all};
+        if (hipMemcpyAsync(s->d_ntiles, counts, sizeof(counts), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+            return LBM_ERR_HIP;
+        // the copy reads a stack array: make it complete before it goes out of scope
         if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_ERR_HIP;
+        // a bundle launches only the kernels with tiles to sweep
+        const bool want_thin = s->n_thin > 0, want_gen = s->n_all > s->n_thin;
+        if (s->graph && (want_thin != s->graph_thin || want_gen != s->graph_gen)) {
+            (void)hipGraphExecDestroy(s->graph);
+            s->graph = nullptr;
+        }
         s->tables_dirty = false;
     }
     if (!s->h_desc.empty() &&
@@ -269,14 +299,21 @@ int upload_tables(lbm_server *s) {
 int capture_graph(lbm_server *s) {
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_ERR_HIP;
+    const bool thin = s->n_thin > 0, gen = s->n_all > s->n_thin;
     int rc = dispatch_serve(s->prm.storage, [&](auto SI) -> int {
         constexpr int S = decltype(SI)::value;
-        using TL = typename TileFor<S>::type;
-        for (int st = 0; st < s->prm.bundle_steps; st++)
-            hipLaunchKernelGGL((k_serve<S>), dim3(s->grid), dim3(TL::NT), 0, s->stream, s->d_desc, s->d_tiles,
-                               s->d_ntiles, st);
+        for (int st = 0; st < s->prm.bundle_steps; st++) {
+            if (thin)
+                hipLaunchKernelGGL((k_serve<S, true>), dim3(s->grid_thin), dim3(ServeTile<S, true>::NT), 0, s->stream, s->d_desc,
+                                   s->d_tiles, s->d_ntiles, st);
+            if (gen)
+                hipLaunchKernelGGL((k_serve<S, false>), dim3(s->grid), dim3(ServeTile<S, false>::NT), 0, s->stream, s->d_desc,
+                                   s->d_tiles, s->d_ntiles, st);
+        }
         return LBM_OK;
     });
+    s->graph_thin = thin;
+    s->graph_gen = gen;
     hipError_t e = hipStreamEndCapture(s->stream, &g);
     if (rc || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -427,7 +464,18 @@ int lbm_server_create(const lbm_server_params *p, void *hip_stream, lbm_server_h
     (void)hipGetDevice(&s->device);
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
-    s->grid = cus > 0 ? cus : 256;  // one 512-thread work-group per CU fits the LDS
+    if (cus <= 0) cus = 256;
+    s->grid = cus;  // the general kernel's LDS admits one 512-thread work-group per CU
+    // the one-plane kernel: as many work-groups per CU as its registers and LDS admit
+    int per_cu = 0;
+    (void)dispatch_serve(p->storage, [&](auto SI) -> int {
+        constexpr int S = decltype(SI)::value;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_serve<S, true>, ServeTile<S, true>::NT, 0) !=
+            hipSuccess)
+            per_cu = 1;
+        return 0;
+    });
+    s->grid_thin = cus * (per_cu > 0 ? per_cu : 1);
     if (hip_stream) {
         s->stream = (hipStream_t)hip_stream;
     } else {
@@ -438,8 +486,8 @@ int lbm_server_create(const lbm_server_params *p, void *hip_stream, lbm_server_h
         s->own_stream = true;
     }
     hipError_t e = hipMalloc(&s->d_desc, sizeof(ServeDesc) * p->max_lattices);
-    if (e == hipSuccess) e = hipMalloc(&s->d_ntiles, sizeof(int));
-    if (e == hipSuccess) e = hipMemset(s->d_ntiles, 0, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&s->d_ntiles, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(s->d_ntiles, 0, 2 * sizeof(int));
     if (e != hipSuccess) {
         lbm_server_destroy(s);
         return set_error(LBM_ERR_OOM, "server tables");
