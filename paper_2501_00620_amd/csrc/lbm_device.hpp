@@ -300,6 +300,21 @@ __device__ __forceinline__ void grad_finish(const GradAcc<C> &g, C F[3], C S[6])
     for (int c = 3; c < 6; c++) S[c] = -(g.fS[c] * C(1.0 / 6.0) + g.eS[c] * C(1.0 / 12.0));
 }
 
+// The same forcing moments on a lattice of one z plane, from the in-plane faces (directions 1-4,
+// in the face sums) and in-plane edges (7-10, in the edge sums) alone: each face offset also
+// stands for the two z edges reading the same site (weight 1/18 + 2/36 = 1/9), whose z parts
+// cancel, and the +-z faces at the site itself cancel.  F = -3 (face/9 + edge/36), S likewise
+// with the diagonal sums doubled.
+template <typename C>
+__device__ __forceinline__ void grad_finish_thin(const GradAcc<C> &g, C F[3], C S[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) F[c] = -(g.fF[c] * C(1.0 / 3.0) + g.eF[c] * C(1.0 / 12.0));
+#pragma unroll
+    for (int c = 0; c < 3; c++) S[c] = -(g.fS[c] * C(2.0 / 3.0) + g.eS[c] * C(1.0 / 6.0));
+#pragma unroll
+    for (int c = 3; c < 6; c++) S[c] = -(g.fS[c] * C(1.0 / 3.0) + g.eS[c] * C(1.0 / 12.0));
+}
+
 // Steps 3-5: corrected moments, equilibria, forcing and the BGK update, in place on the
 // deviations d and beta.  Returns the corrected u and theta = T - T_ref if asked.
 //

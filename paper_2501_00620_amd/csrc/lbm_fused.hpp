@@ -56,13 +56,14 @@ template <int TX_, int TY_> struct Tile {
 #endif
 template <int S> struct TileFor { using type = Tile<FUSED_TX, FUSED_TY>; };
 template <> struct TileFor<0> { using type = Tile<64, 2>; };
-// Tiles of the one-plane serving kernel: it has LDS to spare, and 256-thread work-groups let
-// two of them share a CU at the same register budget, each covering the other's load waits.
+// Tiles of the one-plane serving kernel.  With one LDS slot of each kind (43 KB) and the in-plane
+// arithmetic it fits 128 VGPRs, so two 512-thread work-groups share a CU (four waves per SIMD),
+// each covering the other's load waits.
 #ifndef SERVE_THIN_TX
 #define SERVE_THIN_TX 64
 #endif
 #ifndef SERVE_THIN_TY
-#define SERVE_THIN_TY 4
+#define SERVE_THIN_TY 8
 #endif
 template <int S> struct ThinTileFor { using type = Tile<SERVE_THIN_TX, SERVE_THIN_TY>; };
 
@@ -199,8 +200,10 @@ __device__ __forceinline__ void source_site_gathered(const Buf<S> &bF, const Buf
 
 // Sources of one site whose bbar* neighbourhood is staged in LDS: the gather of Eq. 66 reads
 // the staged planes bs[0..2] (planes z-1, z, z+1); bidx is the site's staging index.
-// The site's populations arrive raw (loaded one plane ahead).
-template <int S, typename TL, bool KEEP>
+// The site's populations arrive raw (loaded one plane ahead).  THIN1 (one z plane): the upstream
+// sites y - e_i of a direction and of its mirror in z coincide, so the gather runs over the 9
+// in-plane offsets with the arriving populations summed per offset first.
+template <int S, typename TL, bool KEEP, bool THIN1 = false>
 __device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typename Buf<S>::R raw[Q],
                                                    const typename Storage<S>::C *__restrict__ Tf,
                                                    typename Storage<S>::C Tconst,
@@ -215,15 +218,34 @@ __device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typen
     C acc[NB];
 #pragma unroll
     for (int c = 0; c < NB; c++) acc[c] = C(0);
-    Unroll<0, Q>::run([&](auto I) {
-        constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
-        const C *pl = bs[1 - ez] + bidx;  // upstream site y - e_i lies in plane z - e_iz
-        constexpr int off = -ey * TL::BX - ex;
-        const C wgt = fma(C(WQ[I]), k.rho_ref, d[I]);
+    if constexpr (THIN1) {
+        // arriving populations summed per in-plane offset (ex, ey), index (ey + 1) * 3 + ex + 1
+        C wg[9];
 #pragma unroll
-        for (int c = 0; c < NB; c++) acc[c] = fma(wgt, pl[c * TL::NB2 + off], acc[c]);
-        if constexpr (I % GATHER_GROUP == GATHER_GROUP - 1) __builtin_amdgcn_sched_barrier(0);
-    });
+        for (int q = 0; q < 9; q++) wg[q] = C(0);
+        Unroll<0, Q>::run([&](auto I) {
+            constexpr int q = (EY[I] + 1) * 3 + EX[I] + 1;
+            wg[q] += fma(C(WQ[I]), k.rho_ref, d[I]);
+        });
+        const C *pl = bs[0] + bidx;
+        Unroll<0, 9>::run([&](auto Q9) {
+            constexpr int ex = (int)Q9 % 3 - 1, ey = (int)Q9 / 3 - 1;
+            constexpr int off = -ey * TL::BX - ex;
+#pragma unroll
+            for (int c = 0; c < NB; c++) acc[c] = fma(wg[Q9], pl[c * TL::NB2 + off], acc[c]);
+            if constexpr (Q9 % 3 == 2) __builtin_amdgcn_sched_barrier(0);
+        });
+    } else {
+        Unroll<0, Q>::run([&](auto I) {
+            constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
+            const C *pl = bs[1 - ez] + bidx;  // upstream site y - e_i lies in plane z - e_iz
+            constexpr int off = -ey * TL::BX - ex;
+            const C wgt = fma(C(WQ[I]), k.rho_ref, d[I]);
+#pragma unroll
+            for (int c = 0; c < NB; c++) acc[c] = fma(wgt, pl[c * TL::NB2 + off], acc[c]);
+            if constexpr (I % GATHER_GROUP == GATHER_GROUP - 1) __builtin_amdgcn_sched_barrier(0);
+        });
+    }
     const C inv = recip(m.rho);
 #pragma unroll
     for (int c = 0; c < NB; c++) beta[c] = acc[c] * inv;
@@ -418,7 +440,7 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
             // ring populations not loaded one plane ahead are loaded just before their use
             // (issued before the tile's own sources, they cost more registers than they save)
             constexpr bool ahead = PIPE && FUSED_PREFETCH_RING;
-            source_site_staged<S, TL, true>(bF, praw, Tf, Tconst, k, cd, zo + ixy, ibidx, bs, lds[slot], iidx, keep);
+            source_site_staged<S, TL, true, THIN1>(bF, praw, Tf, Tconst, k, cd, zo + ixy, ibidx, bs, lds[slot], iidx, keep);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < NRING; j++) {
@@ -428,7 +450,7 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
                         Unroll<0, Q>::run([&](auto I) { rraw[j][I] = bF.template loadraw<I>(roff); });
                     }
                     SiteState<C> dummy;
-                    source_site_staged<S, TL, false>(bF, rraw[j], Tf, Tconst, k, cd, zo + rxy[j], rbidx[j], bs,
+                    source_site_staged<S, TL, false, THIN1>(bF, rraw[j], Tf, Tconst, k, cd, zo + rxy[j], rbidx[j], bs,
                                                      lds[slot], rlidx[j], dummy);
                 }
             }
@@ -449,19 +471,37 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
         load_pops<S>(bF, (zc + ixy) * SB, cd, d);  // issued early, consumed after the gradient
         GradAcc<C> acc;
         grad_init(acc);
-        const C *pm = lds[sm] + iidx, *p0 = lds[s0] + iidx, *pp = lds[sp] + iidx;
-        Unroll<1, Q>::run([&](auto I) {
-            constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
-            const C *pl = ez < 0 ? pm : (ez > 0 ? pp : p0);
-            constexpr int off = ey * TL::HX + ex;
-            C sv[NSRC];
-#pragma unroll
-            for (int c = 0; c < NSRC; c++) sv[c] = pl[c * NS + off];
-            grad_add<C, I, HASK>(acc, sv, k.K);
-            if constexpr (I % GRAD_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
-        });
         C Fv[3], Sv[6];
-        grad_finish(acc, Fv, Sv);
+        if constexpr (THIN1) {
+            // One z plane: the +-z pair at the site itself cancels, and the two z edges at an
+            // in-plane axis offset read the site the face there reads (their z parts cancel,
+            // the in-plane parts double); 8 in-plane neighbours, directions 1-4 and 7-10.
+            const C *p0 = lds[s0] + iidx;
+            Unroll<1, 11>::run([&](auto I) {
+                if constexpr (I != 5 && I != 6) {
+                    constexpr int off = EY[I] * TL::HX + EX[I];
+                    C sv[NSRC];
+#pragma unroll
+                    for (int c = 0; c < NSRC; c++) sv[c] = p0[c * NS + off];
+                    grad_add<C, I, HASK>(acc, sv, k.K);
+                    if constexpr (I % GRAD_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+                }
+            });
+            grad_finish_thin(acc, Fv, Sv);
+        } else {
+            const C *pm = lds[sm] + iidx, *p0 = lds[s0] + iidx, *pp = lds[sp] + iidx;
+            Unroll<1, Q>::run([&](auto I) {
+                constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
+                const C *pl = ez < 0 ? pm : (ez > 0 ? pp : p0);
+                constexpr int off = ey * TL::HX + ex;
+                C sv[NSRC];
+#pragma unroll
+                for (int c = 0; c < NSRC; c++) sv[c] = pl[c * NS + off];
+                grad_add<C, I, HASK>(acc, sv, k.K);
+                if constexpr (I % GRAD_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+            });
+            grad_finish(acc, Fv, Sv);
+        }
         const PopMoments<C> m = pop_moments(d, k.rho_ref);
         collide(d, cur.beta, m, Fv, Sv, cur.theta, k);
         int Zo[3];
@@ -558,7 +598,7 @@ template <int S> __device__ __forceinline__ void report_range(float amax, unsign
 
 // Occupancy: the LDS (about 130 KB of 160 KB for float) admits one 512-thread work-group per
 // CU, i.e. two waves per SIMD.
-template <int S, bool GATHERED, bool HASK>
+template <int S, bool GATHERED, bool HASK, bool THIN1>
 __global__ void __launch_bounds__(TileFor<S>::type::NT) __attribute__((amdgpu_waves_per_eu(FUSED_WAVES_PER_EU)))
 k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
         typename Storage<S>::T *__restrict__ Fo, typename Storage<S>::T *__restrict__ Bo,
@@ -574,7 +614,7 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
     const int ty = L % fg.tiles_y;
     const int chunk = L / fg.tiles_y;
     float amax = 0.0f;
-    sweep_tile<S, GATHERED, HASK>(F, B, Fo, Bo, Tf, Tconst, g, k, cd, fg, tx, ty, chunk, amax);
+    sweep_tile<S, GATHERED, HASK, THIN1>(F, B, Fo, Bo, Tf, Tconst, g, k, cd, fg, tx, ty, chunk, amax);
     report_range<S>(amax, flag);
 }
 
@@ -635,12 +675,21 @@ int launch_fused(const typename Storage<S>::T *F, const typename Storage<S>::T *
     if (blocks > 2147483647LL) return -1;
     const dim3 grid((unsigned)blocks), block(TL::NT);
     const bool hask = k.K != 0;
+    // one z plane: the instantiation with the in-plane gather and gradient (the serving kernel
+    // sweeps such lattices with the same arithmetic)
+    auto go = [&](auto G, auto H, auto T1) {
+        hipLaunchKernelGGL((k_fused<S, decltype(G)::value, decltype(H)::value, decltype(T1)::value>), grid, block, 0,
+                           stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg);
+    };
+    using tt = std::true_type;
+    using ff = std::false_type;
+    const bool thin1 = g.nz == 1;
     if (gathered) {
-        if (hask) hipLaunchKernelGGL((k_fused<S, true, true>), grid, block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg);
-        else hipLaunchKernelGGL((k_fused<S, true, false>), grid, block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg);
+        if (hask) thin1 ? go(tt{}, tt{}, tt{}) : go(tt{}, tt{}, ff{});
+        else thin1 ? go(tt{}, ff{}, tt{}) : go(tt{}, ff{}, ff{});
     } else {
-        if (hask) hipLaunchKernelGGL((k_fused<S, false, true>), grid, block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg);
-        else hipLaunchKernelGGL((k_fused<S, false, false>), grid, block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg);
+        if (hask) thin1 ? go(ff{}, tt{}, tt{}) : go(ff{}, tt{}, ff{});
+        else thin1 ? go(ff{}, ff{}, tt{}) : go(ff{}, ff{}, ff{});
     }
     return 0;
 }

@@ -53,7 +53,7 @@ struct TileRef {
 };
 
 #ifndef SERVE_THIN_WAVES_PER_EU
-#define SERVE_THIN_WAVES_PER_EU 2
+#define SERVE_THIN_WAVES_PER_EU 4
 #endif
 template <int S, bool THIN1>
 using ServeTile = typename std::conditional<THIN1, typename ThinTileFor<S>::type, typename TileFor<S>::type>::type;
