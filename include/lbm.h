@@ -140,7 +140,9 @@ const char *lbm_last_error(void);
 /* Steps taken since the last set_fields / set_state. */
 long lbm_steps_done(lbm_handle h);
 
-/* Device bytes a lattice with these parameters occupies (what lbm_create allocates). */
+/* Device bytes a lattice with these parameters occupies (what lbm_create allocates).  A lattice
+ * switched to the two-pass kernel with lbm_set_kernel(h, 1) allocates 9 more planes of the
+ * compute type at its first step. */
 size_t lbm_lattice_bytes(const lbm_params *p);
 
 /* ---------------------------------------------------------------------------------------------

@@ -149,9 +149,23 @@ int read_clear_flag(lbm_lattice *h, unsigned *val) {
 }
 
 // ---- one step ----------------------------------------------------------------------------------
+// The two-pass step's source planes, allocated on its first use (the fused step keeps the
+// sources in LDS, and the readout uses the idle population buffer).
+int ensure_src(lbm_lattice *h) {
+    if (h->src) return LBM_OK;
+    const hipError_t e = hipMalloc(&h->src, compute_bytes(h->p.storage) * NSRC * (size_t)h->n);
+    if (e != hipSuccess) {
+        h->src = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? LBM_ERR_OOM : LBM_ERR_HIP, "source planes: %s", hipGetErrorString(e));
+    }
+    return LBM_OK;
+}
+
 template <int S> int step_two_pass(lbm_lattice *h) {
     using T = typename Storage<S>::T;
     using C = typename Storage<S>::C;
+    if (int rc = ensure_src(h)) return rc;
     const Geo g = geo(h);
     const StepConst<C> k = step_const<C>(h);
     const T *F = (const T *)h->F[h->cur];
@@ -192,7 +206,7 @@ template <int S> int step_fused(lbm_lattice *h) {
     return LBM_OK;
 }
 
-bool use_fused(const lbm_lattice *h) { return h->kernel != 1 && fused_supported(geo(h)); }
+bool use_fused(const lbm_lattice *h) { return h->kernel != 1 && fused_supported(geo(h), h->p.storage); }
 
 }  // namespace
 
@@ -216,13 +230,16 @@ int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out) {
     h->p = *p;
     h->n = (int)n;
     h->stream = (hipStream_t)hip_stream;
-    const size_t sb = store_bytes(p->storage), cb = compute_bytes(p->storage);
+    const size_t sb = store_bytes(p->storage);
     hipError_t e = hipSuccess;
     for (int b = 0; b < 2 && e == hipSuccess; b++) {
         e = hipMalloc(&h->F[b], sb * Q * (size_t)n);
         if (e == hipSuccess) e = hipMalloc(&h->B[b], sb * NB * (size_t)n);
     }
-    if (e == hipSuccess) e = hipMalloc(&h->src, cb * NSRC * (size_t)n);
+    // shapes beyond the fused sweep's range step with the two-pass kernel, which needs its
+    // source planes (others allocate them if lbm_set_kernel asks for the two-pass kernel)
+    if (e == hipSuccess && !fused_supported(geo(h), p->storage))
+        e = hipMalloc(&h->src, compute_bytes(p->storage) * NSRC * (size_t)n);
     if (e == hipSuccess) e = hipMalloc((void **)&h->partial, sizeof(double) * 2 * RED_MAX_BLOCKS * RED_K);
     if (e == hipSuccess) e = hipMalloc((void **)&h->red_out, sizeof(double) * RED_K);
     if (e == hipSuccess) e = hipMalloc((void **)&h->flag, sizeof(unsigned));
@@ -259,7 +276,8 @@ void lbm_destroy(lbm_handle h) {
 
 int lbm_set_kernel(lbm_handle h, int kernel) {
     if (!h || kernel < 0 || kernel > 2) return fail(LBM_ERR_ARG, "bad kernel choice");
-    if (kernel == 2 && !fused_supported(geo(h))) return fail(LBM_ERR_ARG, "fused sweep does not support this lattice shape");
+    if (kernel == 2 && !fused_supported(geo(h), h->p.storage))
+        return fail(LBM_ERR_ARG, "fused sweep does not support this lattice shape");
     h->kernel = kernel;
     return LBM_OK;
 }
@@ -269,7 +287,9 @@ long lbm_steps_done(lbm_handle h) { return h ? h->steps : -1; }
 size_t lbm_lattice_bytes(const lbm_params *p) {
     if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1 || p->storage < 0 || p->storage > 3) return 0;
     const size_t n = (size_t)p->nx * p->ny * p->nz;
-    return 2 * (size_t)NFIELD * store_bytes(p->storage) * n + NSRC * compute_bytes(p->storage) * n +
+    const Geo g{p->nx, p->ny, p->nz, (int)std::min<size_t>(n, 2147483647)};
+    const bool two_pass = !fused_supported(g, p->storage);  // the two-pass step adds its sources
+    return 2 * (size_t)NFIELD * store_bytes(p->storage) * n + (two_pass ? NSRC * compute_bytes(p->storage) * n : 0) +
            sizeof(double) * (2 * RED_MAX_BLOCKS * RED_K + RED_K) + sizeof(unsigned) +
            (p->mode == LBM_ISO ? compute_bytes(p->storage) * n : 0);
 }
@@ -409,7 +429,10 @@ int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on
         const StepConst<C> k = step_const<C>(h);
         const TT *F = (const TT *)h->F[h->cur];
         const TT *B = (const TT *)h->B[h->cur];
-        C *src = (C *)h->src;
+        // the predictor sources of the readout go to the idle population buffer: between steps
+        // it holds nothing, and its 19 planes of storage type hold the 9 of compute type
+        static_assert(NSRC * sizeof(C) <= Q * sizeof(TT), "source planes exceed the idle buffer");
+        C *src = (C *)h->F[1 - h->cur];
         const dim3 grid(blocks_for(h->n)), block(BLOCK);
         auto launch = [&](auto GI, auto OI) {
             constexpr bool G = decltype(GI)::value;

@@ -660,8 +660,13 @@ template <int S> inline FusedGeo fused_geometry(const Geo &g, int slots) {
 template <int S> inline bool fused_supported_s(const Geo &g) {
     return (unsigned long long)Buf<S>::PPG * (unsigned long long)g.n * sizeof(typename Storage<S>::T) < (1ull << 32);
 }
-inline bool fused_supported(const Geo &g) {
-    return fused_supported_s<0>(g);  // the strictest storage (8-byte) bounds them all
+inline bool fused_supported(const Geo &g, int storage) {
+    switch (storage) {
+    case 0: return fused_supported_s<0>(g);
+    case 1: return fused_supported_s<1>(g);
+    case 2: return fused_supported_s<2>(g);
+    default: return fused_supported_s<3>(g);
+    }
 }
 
 template <int S>
