@@ -9,7 +9,8 @@ Also reported on the same JSON line:
   roofline      algorithmic bytes per step (2 x 25 values x 4 B per site) over the measured
                 average step duration, against the 8 TB/s HBM peak; `traffic` from the committed
                 rocprofv3 FETCH_SIZE / WRITE_SIZE counters when they match the current kernel
-                sources, else null;
+                sources, else null; `copy_ceiling`, the GB/s of a plain 1 GiB device copy
+                measured in the same run, and the achieved rate as a fraction of it;
   variants      the 2000-step run in FP64, FP32, FP16- and BF16-deviation storage: MLUPS and the
                 relative L2 error of rho, u, T against the FP64-storage run, kinetic-energy decay;
   served        the served batch: 512 independent four-quadrant Riemann problems (n x n x 1,
@@ -209,6 +210,27 @@ def cpu_baseline(seconds=10.0, n=48, mach=0.5, tau=0.55):
                       f"({dt:.1f} s) on {threads} OpenMP threads"}
 
 
+def copy_ceiling(nbytes=1 << 30, reps=10):
+    """Bandwidth of a plain device copy (bytes read + written per second): the rate this GPU's
+    HBM sustains for a simple stream, beside the 8 TB/s peak."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    secs = e0.elapsed_time(e1) / 1e3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes * reps / secs / 1e9
+
+
 def copy_calibration(nbytes=1 << 30, reps=5):
     """A plain device copy of known size, for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -271,6 +293,7 @@ def main():
     traffic = traffic_from_profiles(kname, workload, sites)
     del lat
     torch.cuda.empty_cache()
+    copy_gbs = copy_ceiling()
 
     line = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
@@ -284,7 +307,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "algorithmic_bytes_per_launch": bytes_per_step},
+                     "algorithmic_bytes_per_launch": bytes_per_step,
+                     "copy_ceiling": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
     }
     if not args.quick:
         line["variants"] = run_variants(n, args.variant_steps, tau, mach)

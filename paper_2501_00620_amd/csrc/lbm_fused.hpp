@@ -141,7 +141,9 @@ template <int S> struct Buf {
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0)), v),
                                                   rs, off, so, 0);
         } else if constexpr (S == 1) {
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, so, 0);
+            // non-temporal (cache-policy bit NT): in single precision the stores would otherwise
+            // evict from L2 the populations the collision reads a second time
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, so, 2);
         } else if constexpr (S == 2) {
             const float h = v * cd.inv[F0 + K];
             amax = fmaxf(amax, fabsf(h));
