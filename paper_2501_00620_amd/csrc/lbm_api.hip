@@ -249,10 +249,21 @@ int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out) {
         (void)hipGetLastError();
         return fail(e == hipErrorOutOfMemory ? LBM_ERR_OOM : LBM_ERR_HIP, "allocation: %s", hipGetErrorString(e));
     }
+    // resident fused work-groups: CUs x work-groups per CU (the runtime's occupancy of the
+    // steady-state kernel of this storage)
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-        h->slots = cus;
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+        int per_cu = 0;
+        (void)dispatch_storage(p->storage, [&](auto SI) -> int {
+            constexpr int S = decltype(SI)::value;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<S, false, false, false>,
+                                                             TileFor<S>::type::NT, 0) != hipSuccess)
+                per_cu = 1;
+            return LBM_OK;
+        });
+        h->slots = cus * (per_cu > 0 ? per_cu : 1);
+    }
     codec_defaults(h);
     *out = h;
     return LBM_OK;

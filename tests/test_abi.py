@@ -55,6 +55,8 @@ def test_no_cpu_fallback_without_a_device():
     from paper_2501_00620_amd import lbm
     with pytest.raises(RuntimeError):
         lbm.Lattice(4, 4, 4, 0.7)
+    with pytest.raises(RuntimeError):
+        lbm.Server(budget_bytes=1 << 30)
 
 
 def test_product_package_does_not_reach_the_oracle():
@@ -73,3 +75,22 @@ def test_error_codes_match_header():
     codes = {m[0]: int(m[1]) for m in re.findall(r"#define LBM_(ERR_\w+|OK)\s+\(?(-?\d+)\)?", src)}
     for code, name in lbm.ERRORS.items():
         assert codes["ERR_" + name] == code
+
+
+def test_lattice_bytes_is_the_state_plus_small_scratch():
+    # host-side accounting behind the server's memory budget: 2 x 25 stored values per site,
+    # source planes only where the fused sweep cannot take the lattice, one more compute-type
+    # plane for a prescribed (ISO) temperature field
+    from paper_2501_00620_amd import lbm
+    scratch = 8 * (2 * 1024 * 32 + 32) + 4
+    n = 256 ** 3
+    assert lbm.lattice_bytes(256, 256, 256, "f32") == 200 * n + scratch
+    assert lbm.lattice_bytes(256, 256, 256, "f16dev") == 100 * n + scratch
+    assert lbm.lattice_bytes(256, 256, 256, "bf16dev") == 100 * n + scratch
+    assert lbm.lattice_bytes(256, 256, 256, "f64") == 400 * n + scratch
+    assert lbm.lattice_bytes(64, 64, 1, "f32", mode="iso") == (200 + 4) * 64 * 64 + scratch
+    # beyond the fused range (the FP32 descriptor groups of 5 planes reach 4 GiB past 2^32/20
+    # sites), the two-pass kernel's 9 source planes are part of the lattice
+    big = 1024 * 1024 * 256
+    assert big * 20 >= 1 << 32
+    assert lbm.lattice_bytes(1024, 1024, 256, "f32") == (200 + 36) * big + scratch
