@@ -541,3 +541,86 @@ int orc_step_sites(int nx, int ny, int nz, double tau, int mode, const double *T
     free(src);
     return 0;
 }
+
+
+/* ---------------------------------------------------------------------------------------------
+ * Standard lattice Boltzmann comparator (Sec. I, Eq. 4): D3Q19 populations without a variance,
+ * equilibrium = the second-order Hermite expansion of the Maxwell-Boltzmann distribution at
+ * temperature T, written in lattice units (c = 1, so 1/c_s^2 = 3 and the Hermite temperature
+ * offset is T - 1/3):
+ *     feq_i = rho w_i [1 + 3 e_i.u + 9/2 (u_a u_b + (T - 1/3) delta_ab)(e_ia e_ib - delta_ab/3)].
+ * The paper uses it as the contrast to the bump scheme in the Galilean-invariance experiment of
+ * Sec. III C.  One step: BGK with the same relaxation factor omega = 1/(tau + 1/2) (Eq. 55
+ * without forcing), then streaming; T is a prescribed field.
+ * ------------------------------------------------------------------------------------------- */
+void orc_feq_std(double rho, double ux, double uy, double uz, double T, double *f)
+{
+    const double u[3] = {ux, uy, uz};
+    for (int i = 0; i < Q; i++) {
+        double eu = 0.0, second = 0.0;
+        for (int a = 0; a < 3; a++) eu += E[i][a] * u[a];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                const double d = a == b ? 1.0 : 0.0;
+                second += (u[a] * u[b] + (T - 1.0 / 3.0) * d) * (E[i][a] * E[i][b] - d / 3.0);
+            }
+        f[i] = rho * W[i] * (1.0 + 3.0 * eu + 4.5 * second);
+    }
+}
+
+void orc_init_std(int nx, int ny, int nz, const double *rho, const double *u, const double *T, double *F)
+{
+    const long n = (long)nx * ny * nz;
+    for (long s = 0; s < n; s++) {
+        double feq[Q];
+        orc_feq_std(rho[s], u[s], u[n + s], u[2 * n + s], T[s], feq);
+        for (int i = 0; i < Q; i++) F[i * n + s] = feq[i];
+    }
+}
+
+int orc_step_std(int nx, int ny, int nz, double tau, const double *Tf, double *F, long nsteps)
+{
+    const long n = (long)nx * ny * nz;
+    const double omega = 1.0 / (tau + 0.5);
+    double *Fp = malloc(sizeof(double) * Q * n);
+    if (!Fp) return -1;
+    for (long it = 0; it < nsteps; it++) {
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < ny; y++)
+                for (int x = 0; x < nx; x++) {
+                    const long s = site(nx, ny, x, y, z);
+                    double rho = 0.0, j[3] = {0.0, 0.0, 0.0}, feq[Q];
+                    for (int i = 0; i < Q; i++) {
+                        const double fi = F[i * n + s];
+                        rho += fi;
+                        for (int a = 0; a < 3; a++) j[a] += fi * E[i][a];
+                    }
+                    orc_feq_std(rho, j[0] / rho, j[1] / rho, j[2] / rho, Tf[s], feq);
+                    for (int i = 0; i < Q; i++) {
+                        const double fi = F[i * n + s];
+                        const long to = site(nx, ny, wrap(x + E[i][0], nx), wrap(y + E[i][1], ny),
+                                             wrap(z + E[i][2], nz));
+                        Fp[i * n + to] = fi - omega * (fi - feq[i]);
+                    }
+                }
+        for (long k = 0; k < Q * n; k++) F[k] = Fp[k];
+    }
+    free(Fp);
+    return 0;
+}
+
+/* Moments of the standard model: rho = sum f, u = sum f e / rho. */
+void orc_moments_std(int nx, int ny, int nz, const double *F, double *rho, double *u)
+{
+    const long n = (long)nx * ny * nz;
+    for (long s = 0; s < n; s++) {
+        double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < Q; i++) {
+            r += F[i * n + s];
+            for (int a = 0; a < 3; a++) j[a] += F[i * n + s] * E[i][a];
+        }
+        rho[s] = r;
+        for (int a = 0; a < 3; a++) u[a * n + s] = j[a] / r;
+    }
+}

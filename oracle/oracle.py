@@ -43,6 +43,11 @@ def _load():
         _lib.orc_invariants.argtypes = [i, i, i, P, P, P]
         _lib.orc_step_sites.argtypes = [i, i, i, d, i, P, P, P, l, C.POINTER(C.c_long), P, P, P]
         _lib.orc_step_sites.restype = i
+        _lib.orc_feq_std.argtypes = [d, d, d, d, d, P]
+        _lib.orc_init_std.argtypes = [i, i, i, P, P, P, P]
+        _lib.orc_step_std.argtypes = [i, i, i, d, P, P, l]
+        _lib.orc_step_std.restype = i
+        _lib.orc_moments_std.argtypes = [i, i, i, P, P, P]
     return _lib
 
 
@@ -67,6 +72,13 @@ def feq(rho, ux, uy, uz):
     out = np.zeros(19)
     _load().orc_feq(float(rho), float(ux), float(uy), float(uz), _p(out))
     return out
+
+
+def feq_std(rho, ux, uy, uz, T):
+    """Equilibrium of the standard lattice Boltzmann comparator (Sec. I, Eq. 4), lattice units."""
+    f = np.zeros(19)
+    _load().orc_feq_std(float(rho), float(ux), float(uy), float(uz), float(T), _p(f))
+    return f
 
 
 def beq(ux, uy, uz, T):
@@ -98,7 +110,9 @@ def gradient(phi, axis):
     return out
 
 
-MODES = {"thermal": 0, "iso": 1}
+# thermal: temperature from the total second moment; iso: prescribed temperature field;
+# standard: the standard lattice Boltzmann comparator (Sec. I, Eq. 4; no variance, prescribed T)
+MODES = {"thermal": 0, "iso": 1, "standard": 2}
 
 
 class OracleLattice:
@@ -125,9 +139,13 @@ class OracleLattice:
         rho = _f64(np.broadcast_to(rho, self.shape))
         u = _f64(np.broadcast_to(u, (3,) + self.shape))
         T = _f64(np.broadcast_to(T, self.shape))
-        if self.mode == 1:
+        if self.mode in (1, 2):
             self.T_field = T.copy()
-        _load().orc_init(self.nx, self.ny, self.nz, _p(rho), _p(u), _p(T), _p(self.F), _p(self.b))
+        if self.mode == 2:
+            self.b = np.zeros((6,) + self.shape)
+            _load().orc_init_std(self.nx, self.ny, self.nz, _p(rho), _p(u), _p(T), _p(self.F))
+        else:
+            _load().orc_init(self.nx, self.ny, self.nz, _p(rho), _p(u), _p(T), _p(self.F), _p(self.b))
         self.steps = 0
 
     def set_state(self, F, b):
@@ -138,8 +156,11 @@ class OracleLattice:
         return self.F.copy(), self.b.copy()
 
     def step(self, n=1):
-        rc = _load().orc_step(self.nx, self.ny, self.nz, self.tau, self.mode, _p(self.T_field),
-                              _p(self.F), _p(self.b), int(n))
+        if self.mode == 2:
+            rc = _load().orc_step_std(self.nx, self.ny, self.nz, self.tau, _p(self.T_field), _p(self.F), int(n))
+        else:
+            rc = _load().orc_step(self.nx, self.ny, self.nz, self.tau, self.mode, _p(self.T_field),
+                                  _p(self.F), _p(self.b), int(n))
         if rc != 0:
             raise MemoryError("oracle step failed")
         self.steps += int(n)
@@ -148,6 +169,9 @@ class OracleLattice:
         rho = np.zeros(self.shape)
         u = np.zeros((3,) + self.shape)
         T = np.zeros(self.shape)
+        if self.mode == 2:
+            _load().orc_moments_std(self.nx, self.ny, self.nz, _p(self.F), _p(rho), _p(u))
+            return rho, u, self.T_field.copy()
         rc = _load().orc_moments(self.nx, self.ny, self.nz, self.tau, self.mode, _p(self.T_field),
                                  _p(self.F), _p(self.b), _p(rho), _p(u), _p(T))
         if rc != 0:
