@@ -54,8 +54,11 @@ typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2, LBM_BF16DEV = 3 } lbm_s
 /* Temperature closure.  THERMAL: T from the total second-moment trace of the bump expansion
  * (Eq. 26), so mass, momentum and energy are conserved.  ISO: T is the prescribed per-site field
  * given to lbm_set_fields (the paper's setting in all its experiments); mass and momentum are
- * conserved. */
-typedef enum { LBM_THERMAL = 0, LBM_ISO = 1 } lbm_mode;
+ * conserved.  STANDARD: the standard lattice Boltzmann comparator the paper contrasts with its
+ * scheme (Sec. I, Eq. 4; Sec. III C): populations without a variance, the second-order Hermite
+ * equilibrium feq_i = rho w_i [1 + 3 e.u + 9/2 (u u + (T - 1/3) I):(e e - I/3)] at the prescribed
+ * T, BGK with the same omega = 1/(tau + 1/2); bbar stays at its reference.  Not served. */
+typedef enum { LBM_THERMAL = 0, LBM_ISO = 1, LBM_STANDARD = 2 } lbm_mode;
 
 /* Field dtypes accepted by set_fields / get_moments. */
 typedef enum { LBM_DTYPE_F64 = 0, LBM_DTYPE_F32 = 1 } lbm_dtype;
@@ -72,13 +75,14 @@ typedef struct {
 typedef struct lbm_lattice *lbm_handle;
 
 /* Allocate a lattice on the current HIP device.  `hip_stream` is a hipStream_t (may be NULL).
- * Device memory: 2 x (19 + 6) values of the storage type per site, plus 9 compute-type values
- * per site of gradient sources.  Errors: ARG, OOM, HIP. */
+ * Device memory: 2 x (19 + 6) values of the storage type per site (lbm_lattice_bytes gives the
+ * total).  Errors: ARG, OOM, HIP. */
 int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out);
 
 /* Initialise from macroscopic fields (Sec. II B, Appendix A): fbar_i = feq_i(rho, u),
- * bbar = beq(u, T) at every site.  rho: n values, u: 3n, T: n, all of `dtype`.  In ISO mode T
- * is also kept as the prescribed temperature field.  For 16-bit storage the codec scales are
+ * bbar = beq(u, T) at every site (STANDARD: the Hermite equilibrium of Eq. 4 at T, bbar at its
+ * reference).  rho: n values, u: 3n, T: n, all of `dtype`.  In ISO and STANDARD mode T is also
+ * kept as the prescribed temperature field.  For 16-bit storage the codec scales are
  * chosen here from the initial deviations.  Errors: ARG (rho <= 0 or non-finite anywhere),
  * RANGE, HIP. */
 int lbm_set_fields(lbm_handle h, const void *rho, const void *u, const void *T, int dtype,
@@ -90,6 +94,7 @@ int lbm_step(lbm_handle h, long n_steps);
 
 /* Read the macroscopic moments of the current state: rho = sum fbar (Eq. 56), the corrected
  * velocity of Eq. 57, and T (the corrected THERMAL temperature, or the prescribed ISO field).
+ * STANDARD: rho, u = sum f e / rho and the prescribed T.
  * rho: n, u: 3n, T: n values of `dtype`.  Any pointer may be NULL to skip that field. */
 int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on_device);
 

@@ -206,6 +206,22 @@ template <int S> int step_fused(lbm_lattice *h) {
     return LBM_OK;
 }
 
+// One step of the standard lattice Boltzmann comparator (Sec. I, Eq. 4): BGK and push.
+template <int S> int step_std(lbm_lattice *h) {
+    using T = typename Storage<S>::T;
+    using C = typename Storage<S>::C;
+    hipLaunchKernelGGL((k_std<S>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream, (const T *)h->F[h->cur],
+                       (T *)h->F[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, geo(h), step_const<C>(h), h->codec,
+                       h->flag);
+    int rc = check_launch();
+    if (rc) return rc;
+    // bbar carries nothing in this model: both buffers hold its reference (zero deviation) since
+    // set_fields
+    h->cur = 1 - h->cur;
+    h->gathered = false;
+    return LBM_OK;
+}
+
 bool use_fused(const lbm_lattice *h) { return h->kernel != 1 && fused_supported(geo(h), h->p.storage); }
 
 }  // namespace
@@ -223,7 +239,8 @@ int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out) {
     if (n > 2147483647LL) return fail(LBM_ERR_ARG, "lattice has more than 2^31-1 sites");
     if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(LBM_ERR_ARG, "tau must be > 0");
     if (p->storage < 0 || p->storage > 3) return fail(LBM_ERR_ARG, "unknown storage %d", p->storage);
-    if (p->mode != LBM_THERMAL && p->mode != LBM_ISO) return fail(LBM_ERR_ARG, "unknown mode %d", p->mode);
+    if (p->mode != LBM_THERMAL && p->mode != LBM_ISO && p->mode != LBM_STANDARD)
+        return fail(LBM_ERR_ARG, "unknown mode %d", p->mode);
     if (!(p->rho_ref > 0.0)) return fail(LBM_ERR_ARG, "rho_ref must be > 0");
     lbm_lattice *h = new (std::nothrow) lbm_lattice();
     if (!h) return fail(LBM_ERR_OOM, "host allocation failed");
@@ -302,7 +319,7 @@ size_t lbm_lattice_bytes(const lbm_params *p) {
     const bool two_pass = !fused_supported(g, p->storage);  // the two-pass step adds its sources
     return 2 * (size_t)NFIELD * store_bytes(p->storage) * n + (two_pass ? NSRC * compute_bytes(p->storage) * n : 0) +
            sizeof(double) * (2 * RED_MAX_BLOCKS * RED_K + RED_K) + sizeof(unsigned) +
-           (p->mode == LBM_ISO ? compute_bytes(p->storage) * n : 0);
+           (p->mode == LBM_ISO || p->mode == LBM_STANDARD ? compute_bytes(p->storage) * n : 0);
 }
 
 int lbm_sync(lbm_handle h) {
@@ -354,7 +371,7 @@ int lbm_set_fields(lbm_handle h, const void *rho, const void *u, const void *T, 
             h->Tf = nullptr;
         }
         bool keepT = false;
-        if (h->p.mode == LBM_ISO) {
+        if (h->p.mode == LBM_ISO || h->p.mode == LBM_STANDARD) {
             // uniform check on the host is cheap for host inputs; device inputs are kept as a field
             if (!on_device) {
                 if (dtype == LBM_DTYPE_F64) {
@@ -380,7 +397,19 @@ int lbm_set_fields(lbm_handle h, const void *rho, const void *u, const void *T, 
             constexpr int S = decltype(SI)::value;
             using TT = typename Storage<S>::T;
             using C = typename Storage<S>::C;
-            if (dtype == LBM_DTYPE_F64)
+            if (h->p.mode == LBM_STANDARD) {
+                if (dtype == LBM_DTYPE_F64)
+                    hipLaunchKernelGGL((k_init_std<S, double>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream,
+                                       (const double *)dr, (const double *)du, (const double *)dT, g, h->codec,
+                                       h->p.rho_ref, h->p.T_ref, (TT *)h->F[0], (TT *)h->B[0], (C *)h->Tf, h->flag);
+                else
+                    hipLaunchKernelGGL((k_init_std<S, float>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream,
+                                       (const float *)dr, (const float *)du, (const float *)dT, g, h->codec,
+                                       h->p.rho_ref, h->p.T_ref, (TT *)h->F[0], (TT *)h->B[0], (C *)h->Tf, h->flag);
+                // the other bbar buffer too: zero bits are a zero deviation in every storage
+                const hipError_t e = hipMemsetAsync(h->B[1], 0, store_bytes(h->p.storage) * NB * n, h->stream);
+                if (e != hipSuccess) return fail(LBM_ERR_HIP, "clearing bbar: %s", hipGetErrorString(e));
+            } else if (dtype == LBM_DTYPE_F64)
                 hipLaunchKernelGGL((k_init<S, double>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream,
                                    (const double *)dr, (const double *)du, (const double *)dT, g, h->codec,
                                    h->p.rho_ref, h->p.T_ref, (TT *)h->F[0], (TT *)h->B[0], (C *)h->Tf, h->flag);
@@ -408,10 +437,11 @@ int lbm_step(lbm_handle h, long n_steps) {
     if (n_steps < 0) return fail(LBM_ERR_ARG, "n_steps < 0");
     if (!h->has_state) return fail(LBM_ERR_STATE, "step before set_fields/set_state");
     const bool fused = use_fused(h);
+    const bool standard = h->p.mode == LBM_STANDARD;
     for (long i = 0; i < n_steps; i++) {
         int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
             constexpr int S = decltype(SI)::value;
-            return fused ? step_fused<S>(h) : step_two_pass<S>(h);
+            return standard ? step_std<S>(h) : fused ? step_fused<S>(h) : step_two_pass<S>(h);
         });
         if (rc) return rc;
         h->steps++;
@@ -448,6 +478,11 @@ int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on
         auto launch = [&](auto GI, auto OI) {
             constexpr bool G = decltype(GI)::value;
             using OUT = typename decltype(OI)::type;
+            if (h->p.mode == LBM_STANDARD) {
+                hipLaunchKernelGGL((k_readout_std<S, OUT>), grid, block, 0, h->stream, F, (const C *)h->Tf,
+                                   (C)h->Tconst, g, k, h->codec, h->p.T_ref, (OUT *)dr, (OUT *)du, (OUT *)dT);
+                return;
+            }
             hipLaunchKernelGGL((k_predict<S, G>), grid, block, 0, h->stream, F, B, src, (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
             hipLaunchKernelGGL((k_readout<S, G, OUT>), grid, block, 0, h->stream, F, B, (const C *)src, (const C *)h->Tf,
                                (C)h->Tconst, g, k, h->codec, h->p.T_ref, (OUT *)dr, (OUT *)du, (OUT *)dT);
@@ -552,8 +587,8 @@ int lbm_get_stored(lbm_handle h, void *F, void *b, int *b_is_gathered, int on_de
 
 int lbm_set_state(lbm_handle h, const void *F, const void *b, int on_device) {
     if (!h || !F || !b) return fail(LBM_ERR_ARG, "null argument");
-    if (h->p.mode == LBM_ISO && !h->has_state)
-        return fail(LBM_ERR_STATE, "ISO mode: set_fields first (it provides the temperature field)");
+    if ((h->p.mode == LBM_ISO || h->p.mode == LBM_STANDARD) && !h->has_state)
+        return fail(LBM_ERR_STATE, "ISO and STANDARD mode: set_fields first (it provides the temperature field)");
     const size_t n = h->n;
     void *stage = nullptr;
     const double *dF = (const double *)F, *dB = (const double *)b;

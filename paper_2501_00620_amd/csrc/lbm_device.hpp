@@ -442,4 +442,21 @@ template <int N> struct Unroll<N, N> {
     template <typename Fn> static __device__ __forceinline__ void run(Fn &&) {}
 };
 
+// Standard lattice Boltzmann comparator (Sec. I, Eq. 4; lattice units, c_s^2 = 1/3): the
+// second-order Hermite equilibrium at temperature T = 1/3 + th, in deviation form
+//   feq_i - w_i rho_ref = w_i (rho - rho_ref)
+//                         + rho w_i [3 e.u + 9/2 (e.u)^2 - 3/2 |u|^2 + 9/2 th (|e|^2 - 1)].
+template <typename C>
+__device__ __forceinline__ void equilibrium_std_dev(C drho, C rho, C ux, C uy, C uz, C th, C f[Q]) {
+    const C u2 = ux * ux + uy * uy + uz * uz;
+    const C a = fma(C(-1.5), u2, C(-4.5) * th);  // the |e|^2 = 0 part of the bracket
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
+        constexpr int e2 = ex * ex + ey * ey + ez * ez;
+        const C eu = C(ex) * ux + C(ey) * uy + C(ez) * uz;
+        const C br = fma(eu, fma(C(4.5), eu, C(3)), fma(C(4.5 * e2), th, a));
+        f[I] = C(WQ[I]) * fma(rho, br, drho);
+    });
+}
+
 }  // namespace lbm

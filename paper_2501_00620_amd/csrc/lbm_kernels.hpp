@@ -190,6 +190,76 @@ k_init(const IN *__restrict__ rho, const IN *__restrict__ u, const IN *__restric
     if (sat) *flag = 1u;
 }
 
+// ---- standard lattice Boltzmann comparator (Sec. I, Eq. 4) ---------------------------------------
+// The populations carry no variance: bbar stays at its reference (deviation 0); T is the
+// prescribed field (theta = T - T_ref per site, or the constant).
+template <int S, typename IN>
+__global__ void __launch_bounds__(BLOCK)
+k_init_std(const IN *__restrict__ rho, const IN *__restrict__ u, const IN *__restrict__ T, Geo g, Codec cd,
+           double rho_ref, double T_ref, typename Storage<S>::T *__restrict__ F, typename Storage<S>::T *__restrict__ B,
+           typename Storage<S>::C *__restrict__ Tf, unsigned *__restrict__ flag) {
+    using C = typename Storage<S>::C;
+    const int s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= g.n) return;
+    const size_t n = g.n;
+    const double r = (double)rho[s], ux = (double)u[s], uy = (double)u[n + s], uz = (double)u[2 * n + s];
+    double f[Q];
+    equilibrium_std_dev(r - rho_ref, r, ux, uy, uz, (double)T[s] - 1.0 / 3.0, f);
+    unsigned sat = 0;
+    Unroll<0, Q>::run([&](auto I) { Storage<S>::store(F, (size_t)I * n + s, I, (C)f[I], cd, sat); });
+#pragma unroll
+    for (int c = 0; c < NB; c++) Storage<S>::store(B, (size_t)c * n + s, Q + c, C(0), cd, sat);
+    if (Tf) Tf[s] = (C)((double)T[s] - T_ref);
+    if (sat) *flag = 1u;
+}
+
+// One step: BGK with the scheme's relaxation factor, d' = (1 - omega) d + omega d_eq, and the
+// push to the 19 neighbours.
+template <int S>
+__global__ void __launch_bounds__(BLOCK)
+k_std(const typename Storage<S>::T *__restrict__ F, typename Storage<S>::T *__restrict__ Fo,
+      const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
+      StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag) {
+    using C = typename Storage<S>::C;
+    const int s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, z;
+    site_xyz(s, g, x, y, z);
+    const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    C d[Q], feq[Q];
+    Unroll<0, Q>::run([&](auto I) { d[I] = Storage<S>::load(F, (size_t)I * g.n + s, I, cd); });
+    const PopMoments<C> m = pop_moments(d, k.rho_ref);
+    const C inv = recip(m.rho);
+    equilibrium_std_dev(m.drho, m.rho, m.jx * inv, m.jy * inv, m.jz * inv, site_T(Tf, Tconst, s) + k.theta_ref, feq);
+    unsigned sat = 0;
+    Unroll<0, Q>::run([&](auto I) {
+        Storage<S>::store(Fo, (size_t)I * g.n + nb.at(EX[I], EY[I], EZ[I]), I, fma(k.om1, d[I], k.omega * feq[I]), cd,
+                          sat);
+    });
+    if (sat) *flag = 1u;
+}
+
+// Moments of the standard model: rho, u = j / rho, and the prescribed T.
+template <int S, typename OUT>
+__global__ void __launch_bounds__(BLOCK)
+k_readout_std(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::C *__restrict__ Tf,
+              typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd, double T_ref,
+              OUT *__restrict__ rho, OUT *__restrict__ u, OUT *__restrict__ T) {
+    using C = typename Storage<S>::C;
+    const int s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= g.n) return;
+    C d[Q];
+    Unroll<0, Q>::run([&](auto I) { d[I] = Storage<S>::load(F, (size_t)I * g.n + s, I, cd); });
+    const PopMoments<C> m = pop_moments(d, k.rho_ref);
+    if (rho) rho[s] = (OUT)((double)k.rho_ref + (double)m.drho);
+    if (u) {
+        u[s] = (OUT)(m.jx / m.rho);
+        u[(size_t)g.n + s] = (OUT)(m.jy / m.rho);
+        u[2 * (size_t)g.n + s] = (OUT)(m.jz / m.rho);
+    }
+    if (T) T[s] = (OUT)(T_ref + (double)site_T(Tf, Tconst, s));
+}
+
 // ---- state codec ------------------------------------------------------------------------------
 template <int S>
 __global__ void __launch_bounds__(BLOCK)
