@@ -19,6 +19,9 @@ Also reported on the same JSON line:
                 storage; p50/p99 time-to-result (per run and over the requests every storage
                 completed), aggregate MLUPS, failed requests with their reasons (strong
                 four-quadrant problems leave the scheme's stability region and diverge);
+  comparator    the standard lattice Boltzmann comparator (Sec. I, Eq. 4) timed on the same
+                input, and the Galilean-invariance contrast measured on the GPU (shear-wave
+                viscosity in a moving frame, bump vs standard scheme);
   cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded sample (a 48^3
                 Taylor-Green vortex for ~10 s).
 
@@ -191,6 +194,54 @@ def run_served_comparison(storages=("f32", "f16dev", "bf16dev"), **kw):
     return out
 
 
+def run_standard(n, tau, mach, steps, warmup):
+    """The standard lattice Boltzmann comparator (mode "standard") on the same Taylor-Green
+    input: one kernel per step moving 2 x 19 values per site (it carries no variance)."""
+    import torch
+    from paper_2501_00620_amd import lbm, workloads
+    rho, u, T = workloads.taylor_green(n, mach=mach)
+    lat = lbm.Lattice(n, n, n, tau, storage="f32", mode="standard")
+    lat.set_fields(rho, u, T)
+    secs = timed_steps(lat, steps, warmup)
+    health = lat.health()
+    del lat
+    torch.cuda.empty_cache()
+    achieved = n ** 3 * 2 * 19 * 4 / (secs / steps) / 1e9
+    print(f"[bench] standard comparator: {n ** 3 * steps / secs / 1e6:.0f} MLUPS", file=sys.stderr, flush=True)
+    return {"mlups": n ** 3 * steps / secs / 1e6, "ms_per_step": secs * 1e3 / steps,
+            "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_site": 2 * 19 * 4,
+            "nonfinite_sites": health[0], "workload": f"Taylor-Green vortex {n}^3, Mach {mach}, tau {tau}, FP32"}
+
+
+def galilean_contrast(U=0.2, N=64, T0=1.0 / 3.0, tau=0.6, steps=2000, every=50):
+    """The paper's Galilean-invariance contrast on the GPU: a shear wave u_y(x) on a background
+    flow U along x decays with nu = T tau in the bump scheme and, by the standard scheme's third
+    moment, with nu = tau (1/3 - U^2) in the standard one.  FP64 storage, N x 1 x 1 lattice."""
+    import numpy as np
+    from paper_2501_00620_amd import lbm
+    k = 2 * np.pi / N
+    x = np.arange(N)
+    out = {"U": U, "T": T0, "tau": tau, "N": N, "predicted_standard": 1 - U * U / T0}
+    for mode in ("thermal", "standard"):
+        lat = lbm.Lattice(N, 1, 1, tau, storage="f64", mode=mode)
+        u = np.zeros((3, 1, 1, N))
+        u[0] = U
+        u[1] = 1e-3 * np.sin(k * x)
+        lat.set_fields(np.ones((1, 1, N)), u, np.full((1, 1, N), T0))
+        ts, amp = [], []
+        for t in range(0, steps + 1, every):
+            if t:
+                lat.step(every)
+            uy = lat.moments()[1][1].cpu().numpy().reshape(N)
+            ts.append(t)
+            amp.append(np.hypot(uy @ np.sin(k * x), uy @ np.cos(k * x)))
+        nu = -np.polyfit(np.array(ts[4:], float), np.log(amp[4:]), 1)[0] / k ** 2
+        out["nu_over_Ttau_" + ("bump" if mode == "thermal" else "standard")] = nu / (T0 * tau)
+    print(f"[bench] Galilean contrast at U={U}: bump {out['nu_over_Ttau_bump']:.4f}, "
+          f"standard {out['nu_over_Ttau_standard']:.4f}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(seconds=10.0, n=48, mach=0.5, tau=0.55):
     import oracle
     from paper_2501_00620_amd import workloads
@@ -313,6 +364,8 @@ def main():
     if not args.quick:
         line["variants"] = run_variants(n, args.variant_steps, tau, mach)
         line["served"] = run_served_comparison(n_requests=args.serve_requests)
+        line["comparator"] = {"standard": run_standard(n, tau, mach, args.steps, args.warmup),
+                              "galilean": galilean_contrast()}
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     else:
         line["cpu_baseline"] = None
