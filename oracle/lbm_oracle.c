@@ -319,8 +319,17 @@ static void correct(int nx, int ny, int nz, double tau, int mode, const double *
     }
 }
 
-/* Collision at one site (steps 4-5): post-collision fbar* (19) and bbar* (6). */
-static void collide(const double *Fs, const double *bs, const corrected *c, double omega,
+/* Collision at one site (steps 4-5): post-collision fbar* (19) and bbar* (6).
+ *
+ * omega_g: relaxation factor of the nine non-hydrodynamic moments, rows 11-19 of Table I
+ * (omega_g = omega is the single-relaxation-time step of Eq. 55).  With a collision matrix
+ * L = M^-1 diag(lambda_a) M in the Table I basis, the general update of the auxiliary populations
+ * (the form with (I + L dt/2)^-1 that leads to Eq. 55) relaxes moment a with
+ * omega_a = lambda_a / (1 + lambda_a / 2) and weighs its forcing moment with 1 - omega_a / 2.
+ * Rows 1-10 (rho, j, the second moments) keep omega, and Phi has no components on rows 11-19,
+ * so this differs from the single-rate update only by (omega - omega_g) (m_a - m_a^eq) on those
+ * rows, mapped back with the inverse of Table I (w_i m^a_i N^a, as in orc_forcing). */
+static void collide(const double *Fs, const double *bs, const corrected *c, double omega, double omega_g,
                     double *Fpost, double *bpost)
 {
     double feq[Q], beq[NB], phi[Q];
@@ -329,6 +338,16 @@ static void collide(const double *Fs, const double *bs, const corrected *c, doub
     orc_forcing(c->Fv, c->S, phi);
     for (int i = 0; i < Q; i++)
         Fpost[i] = Fs[i] - omega * (Fs[i] - feq[i]) + (1.0 - 0.5 * omega) * phi[i];
+    if (omega_g != omega) {
+        for (int a = 10; a < Q; a++) {
+            double ma = 0.0, norm = 0.0;
+            for (int i = 0; i < Q; i++) {
+                ma += TABLE_M[a][i] * (Fs[i] - feq[i]);
+                norm += W[i] * TABLE_M[a][i] * TABLE_M[a][i];
+            }
+            for (int i = 0; i < Q; i++) Fpost[i] += W[i] * TABLE_M[a][i] / norm * (omega - omega_g) * ma;
+        }
+    }
     for (int k = 0; k < NB; k++) bpost[k] = bs[k] - omega * (bs[k] - beq[k]);
 }
 
@@ -350,12 +369,15 @@ void orc_init(int nx, int ny, int nz, const double *rho, const double *u, const 
     }
 }
 
-/* nsteps full steps in place. mode 0 = energy-conserving temperature, 1 = prescribed T field. */
-int orc_step(int nx, int ny, int nz, double tau, int mode, const double *Tf, double *F, double *b,
-             long nsteps)
+/* nsteps full steps in place. mode 0 = energy-conserving temperature, 1 = prescribed T field.
+ * tau_ghost: relaxation time of the non-hydrodynamic moments (rows 11-19 of Table I; see
+ * collide); tau_ghost = tau is the single-relaxation-time scheme of the paper. */
+int orc_step_mrt(int nx, int ny, int nz, double tau, double tau_ghost, int mode, const double *Tf, double *F,
+                 double *b, long nsteps)
 {
     const long n = (long)nx * ny * nz;
     const double omega = 1.0 / (tau + 0.5);
+    const double omega_g = tau_ghost == tau ? omega : 1.0 / (tau_ghost + 0.5);
     double *src = malloc(sizeof(double) * NSRC * n);
     double *Fp = malloc(sizeof(double) * Q * n);
     double *bp = malloc(sizeof(double) * NB * n);
@@ -377,7 +399,7 @@ int orc_step(int nx, int ny, int nz, double tau, int mode, const double *Tf, dou
                     double Fs[Q], bs[NB], Fo[Q], bo[NB];
                     for (int i = 0; i < Q; i++) Fs[i] = F[i * n + s];
                     for (int k = 0; k < NB; k++) bs[k] = b[k * n + s];
-                    collide(Fs, bs, &c, omega, Fo, bo);
+                    collide(Fs, bs, &c, omega, omega_g, Fo, bo);
                     for (int i = 0; i < Q; i++) Fp[i * n + s] = Fo[i];
                     for (int k = 0; k < NB; k++) bp[k * n + s] = bo[k];
                 }
@@ -403,6 +425,13 @@ int orc_step(int nx, int ny, int nz, double tau, int mode, const double *Tf, dou
     free(Fp);
     free(bp);
     return 0;
+}
+
+/* nsteps single-relaxation-time steps (Eq. 55) in place. */
+int orc_step(int nx, int ny, int nz, double tau, int mode, const double *Tf, double *F, double *b,
+             long nsteps)
+{
+    return orc_step_mrt(nx, ny, nz, tau, tau, mode, Tf, F, b, nsteps);
 }
 
 /* Reported moments of the current state: rho, corrected u (3 planes), T (steps 1-3). */
@@ -526,7 +555,7 @@ int orc_step_sites(int nx, int ny, int nz, double tau, int mode, const double *T
             double Fs[Q], bs[NB], Fo[Q], bo[NB];
             for (int q = 0; q < Q; q++) Fs[q] = Fb[q * nb + su];
             for (int k = 0; k < NB; k++) bs[k] = bb[k * nb + su];
-            collide(Fs, bs, &c, omega, Fo, bo);
+            collide(Fs, bs, &c, omega, omega, Fo, bo);
             Fout[m * Q + i] = Fo[i];
             rho += Fo[i];
             for (int k = 0; k < NB; k++) acc[k] += Fo[i] * bo[k];

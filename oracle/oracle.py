@@ -36,6 +36,8 @@ def _load():
         _lib.orc_init.argtypes = [i, i, i, P, P, P, P, P]
         _lib.orc_step.argtypes = [i, i, i, d, i, P, P, P, l]
         _lib.orc_step.restype = i
+        _lib.orc_step_mrt.argtypes = [i, i, i, d, d, i, P, P, P, l]
+        _lib.orc_step_mrt.restype = i
         _lib.orc_moments.argtypes = [i, i, i, d, i, P, P, P, P, P, P]
         _lib.orc_moments.restype = i
         _lib.orc_forcing_moments.argtypes = [i, i, i, d, i, P, P, P, P, P]
@@ -118,10 +120,13 @@ MODES = {"thermal": 0, "iso": 1, "standard": 2}
 class OracleLattice:
     """A periodic nx*ny*nz lattice stepped by the oracle, state held in numpy arrays."""
 
-    def __init__(self, nx, ny, nz, tau, mode="thermal", T_field=None):
+    def __init__(self, nx, ny, nz, tau, mode="thermal", T_field=None, tau_ghost=None):
+        """tau_ghost: relaxation time of the non-hydrodynamic moments (rows 11-19 of Table I);
+        None keeps the single relaxation time tau."""
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.n = self.nx * self.ny * self.nz
         self.tau = float(tau)
+        self.tau_ghost = self.tau if tau_ghost is None else float(tau_ghost)
         self.mode = MODES[mode]
         shape = (self.nz, self.ny, self.nx)
         self.F = np.zeros((19,) + shape)
@@ -159,8 +164,8 @@ class OracleLattice:
         if self.mode == 2:
             rc = _load().orc_step_std(self.nx, self.ny, self.nz, self.tau, _p(self.T_field), _p(self.F), int(n))
         else:
-            rc = _load().orc_step(self.nx, self.ny, self.nz, self.tau, self.mode, _p(self.T_field),
-                                  _p(self.F), _p(self.b), int(n))
+            rc = _load().orc_step_mrt(self.nx, self.ny, self.nz, self.tau, self.tau_ghost, self.mode,
+                                      _p(self.T_field), _p(self.F), _p(self.b), int(n))
         if rc != 0:
             raise MemoryError("oracle step failed")
         self.steps += int(n)
