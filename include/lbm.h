@@ -135,6 +135,14 @@ int lbm_health(lbm_handle h, long counts[2], double *max_u);
  * buffer, then gradient + collision), 2 = fused z-marching sweep with LDS planes of sources. */
 int lbm_set_kernel(lbm_handle h, int kernel);
 
+/* Relaxation time of the nine non-hydrodynamic moments, rows 11-19 of Table I (Appendix B):
+ * with a collision matrix diagonal in that basis (the general form of the update the paper
+ * reduces to Eq. 55), these moments relax with omega_g = 1/(tau_ghost + 1/2) while rows 1-10
+ * keep omega = 1/(tau + 1/2).  tau_ghost = tau restores the single-rate scheme.  A lattice with
+ * its own ghost rate steps with the two-pass kernel.  Errors: ARG (tau_ghost <= 0 or
+ * non-finite, STANDARD mode, or the fused kernel forced by lbm_set_kernel). */
+int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost);
+
 /* Block until all work queued on the lattice's stream is done. */
 int lbm_sync(lbm_handle h);
 void lbm_destroy(lbm_handle h);

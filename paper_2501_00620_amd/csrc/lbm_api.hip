@@ -77,6 +77,7 @@ template <typename C> StepConst<C> step_const(const lbm_lattice *h) {
     k.theta_ref = (C)(h->p.T_ref - 1.0 / 3.0);
     k.K = (C)(h->p.rho_ref * (h->p.T_ref - 1.0 / 3.0));
     k.om1 = (C)(1.0 - omega);
+    k.ghost = h->tau_ghost > 0.0 ? (C)(1.0 - (1.0 / (h->tau_ghost + 0.5)) / omega) : C(0);
     k.iso = h->p.mode == LBM_ISO;
     return k;
 }
@@ -178,10 +179,16 @@ template <int S> int step_two_pass(lbm_lattice *h) {
     const dim3 grid(blocks_for(h->n)), block(BLOCK);
     if (h->gathered) {
         hipLaunchKernelGGL((k_predict<S, true>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k, h->codec);
-        hipLaunchKernelGGL((k_collide<S, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
+        if (h->tau_ghost > 0.0)
+            hipLaunchKernelGGL((k_collide<S, true, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
+        else
+            hipLaunchKernelGGL((k_collide<S, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
     } else {
         hipLaunchKernelGGL((k_predict<S, false>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k, h->codec);
-        hipLaunchKernelGGL((k_collide<S, false>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
+        if (h->tau_ghost > 0.0)
+            hipLaunchKernelGGL((k_collide<S, false, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
+        else
+            hipLaunchKernelGGL((k_collide<S, false>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
     }
     int rc = check_launch();
     if (rc) return rc;
@@ -222,7 +229,10 @@ template <int S> int step_std(lbm_lattice *h) {
     return LBM_OK;
 }
 
-bool use_fused(const lbm_lattice *h) { return h->kernel != 1 && fused_supported(geo(h), h->p.storage); }
+// the fused sweep relaxes with a single rate; a lattice with its own ghost rate steps two-pass
+bool use_fused(const lbm_lattice *h) {
+    return h->kernel != 1 && h->tau_ghost <= 0.0 && fused_supported(geo(h), h->p.storage);
+}
 
 }  // namespace
 
@@ -306,7 +316,19 @@ int lbm_set_kernel(lbm_handle h, int kernel) {
     if (!h || kernel < 0 || kernel > 2) return fail(LBM_ERR_ARG, "bad kernel choice");
     if (kernel == 2 && !fused_supported(geo(h), h->p.storage))
         return fail(LBM_ERR_ARG, "fused sweep does not support this lattice shape");
+    if (kernel == 2 && h->tau_ghost > 0.0)
+        return fail(LBM_ERR_ARG, "the fused sweep relaxes with a single rate (a ghost rate is set)");
     h->kernel = kernel;
+    return LBM_OK;
+}
+
+int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (!(tau_ghost > 0.0) || !std::isfinite(tau_ghost)) return fail(LBM_ERR_ARG, "tau_ghost must be > 0");
+    if (h->p.mode == LBM_STANDARD) return fail(LBM_ERR_ARG, "the standard comparator relaxes with a single rate");
+    if (h->kernel == 2 && tau_ghost != h->p.tau)
+        return fail(LBM_ERR_ARG, "the fused sweep relaxes with a single rate (lbm_set_kernel chose it)");
+    h->tau_ghost = tau_ghost == h->p.tau ? -1.0 : tau_ghost;
     return LBM_OK;
 }
 

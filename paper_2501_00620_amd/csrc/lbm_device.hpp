@@ -142,6 +142,7 @@ template <typename C> struct StepConst {
     C theta_ref;  // T_ref - 1/3, the diagonal of b_ref
     C K;          // rho_ref * theta_ref
     C om1;        // 1 - omega
+    C ghost;      // 1 - omega_g / omega: the non-hydrodynamic moments' own rate (0: single rate)
     int iso;      // prescribed temperature (theta per site or constant)
 };
 
@@ -441,6 +442,56 @@ template <int I, int N> struct Unroll {
 template <int N> struct Unroll<N, N> {
     template <typename Fn> static __device__ __forceinline__ void run(Fn &&) {}
 };
+
+// Rows 11-19 of Table I (Appendix B), the non-hydrodynamic moments, each scaled to integers
+// (a row's scale cancels in ghost_relax).
+constexpr int GHOST_ROWS[9][Q] = {
+    {0, -2, 0, 2, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0},
+    {0, 0, -2, 0, 2, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1},
+    {0, 0, 0, 0, 0, -2, 2, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1},
+    {0, 0, 0, 0, 0, 0, 0, 1, 1, -1, -1, -1, -1, 1, 1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, -1, -1, 1, 1},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, -1, 1},
+    {0, 1, 1, 1, 1, -2, -2, -2, -2, -2, -2, 1, 1, 1, 1, 1, 1, 1, 1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0, 0, 0, -1, -1, -1, -1, 1, 1, 1, 1},
+    {1, -2, -2, -2, -2, -2, -2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+};
+constexpr double ghost_norm(int a) {  // sum_j w_j r_j^2 of ghost row a
+    double s = 0.0;
+    for (int j = 0; j < Q; j++) s += WQ[j] * GHOST_ROWS[a][j] * GHOST_ROWS[a][j];
+    return s;
+}
+
+// Relaxation of the non-hydrodynamic moments at their own rate omega_g (Table I rows 11-19),
+// applied after the single-rate collision d0 -> d.  In the Table I basis the rates are diagonal,
+// Phi has no components on these rows, and rows 1-10 keep omega, so the update differs from the
+// single-rate one by (omega - omega_g) m_a(d0 - deq) on each ghost row a, mapped back with the
+// inverse of Table I (w_i r_i / sum_j w_j r_j^2).  The single-rate step gives
+// m_a(d0 - deq) = m_a(d0 - d) / omega, so with cg = 1 - omega_g / omega
+//   d_i += cg w_i r_i sum_j r_j (d0_j - d_j) / sum_j w_j r_j^2.
+template <typename C>
+__device__ __forceinline__ void ghost_relax(const C d0[Q], C d[Q], C cg) {
+    C delta[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) delta[i] = d0[i] - d[i];
+    C add[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) add[i] = C(0);
+    Unroll<0, 9>::run([&](auto A) {
+        C m = C(0);
+        Unroll<0, Q>::run([&](auto J) {
+            constexpr int r = GHOST_ROWS[A][J];
+            if constexpr (r != 0) m = fma(C(r), delta[J], m);
+        });
+        const C g = m * (cg * C(1.0 / ghost_norm(A)));
+        Unroll<0, Q>::run([&](auto I) {
+            constexpr int r = GHOST_ROWS[A][I];
+            if constexpr (r != 0) add[I] = fma(C(WQ[I] * r), g, add[I]);
+        });
+    });
+#pragma unroll
+    for (int i = 0; i < Q; i++) d[i] += add[i];
+}
 
 // Standard lattice Boltzmann comparator (Sec. I, Eq. 4; lattice units, c_s^2 = 1/3): the
 // second-order Hermite equilibrium at temperature T = 1/3 + th, in deviation form

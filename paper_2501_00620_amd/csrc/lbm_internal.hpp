@@ -26,6 +26,7 @@ struct lbm_lattice {
     unsigned *flag = nullptr;   // saturation flag
     int kernel = 0;
     int slots = 256;            // fused work-groups resident at once (one per CU)
+    double tau_ghost = -1.0;    // relaxation time of Table I rows 11-19 (<= 0: the single rate)
 };
 
 namespace lbm {

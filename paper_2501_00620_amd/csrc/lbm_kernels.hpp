@@ -109,7 +109,8 @@ __device__ __forceinline__ void gradient_from_src(const C *__restrict__ src, siz
 }
 
 // ---- pass B: gradients, collision, push-stream ------------------------------------------------
-template <int S, bool GATHERED>
+// MRT: the non-hydrodynamic moments relax at their own rate (ghost_relax).
+template <int S, bool GATHERED, bool MRT = false>
 __global__ void __launch_bounds__(BLOCK)
 k_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
           const typename Storage<S>::C *__restrict__ src, typename Storage<S>::T *__restrict__ Fo,
@@ -127,7 +128,13 @@ k_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S
     load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, f, bbar, m);
     C Fv[3], Sv[6];
     gradient_from_src(src, g.n, nb, k.K, Fv, Sv);
+    C f0[MRT ? Q : 1];
+    if constexpr (MRT) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) f0[i] = f[i];
+    }
     collide(f, bbar, m, Fv, Sv, site_T(Tf, Tconst, s), k);
+    if constexpr (MRT) ghost_relax(f0, f, k.ghost);
     unsigned sat = 0;
     Unroll<0, Q>::run([&](auto I) {
         Storage<S>::store(Fo, (size_t)I * g.n + nb.at(EX[I], EY[I], EZ[I]), I, f[I], cd, sat);

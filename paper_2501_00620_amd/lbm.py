@@ -50,6 +50,7 @@ SIGNATURES = {
     "lbm_invariants": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
     "lbm_health": ([C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_double)], C.c_int),
     "lbm_set_kernel": ([C.c_void_p, C.c_int], C.c_int),
+    "lbm_set_ghost_relaxation": ([C.c_void_p, C.c_double], C.c_int),
     "lbm_sync": ([C.c_void_p], C.c_int),
     "lbm_destroy": ([C.c_void_p], None),
     "lbm_last_error": ([], C.c_char_p),
@@ -162,6 +163,11 @@ class Lattice:
 
     def set_kernel(self, kernel):
         _check(_lib.lbm_set_kernel(self._h, KERNEL[kernel] if isinstance(kernel, str) else int(kernel)))
+
+    def set_ghost_relaxation(self, tau_ghost):
+        """Relaxation time of the non-hydrodynamic moments (Table I rows 11-19); tau_ghost = tau
+        is the single-rate scheme.  Such a lattice steps with the two-pass kernel."""
+        _check(_lib.lbm_set_ghost_relaxation(self._h, float(tau_ghost)))
 
     # -- fields and state -------------------------------------------------------------------------
     def _sync_torch(self):
