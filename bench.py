@@ -20,8 +20,9 @@ Also reported on the same JSON line:
                 completed), aggregate MLUPS, failed requests with their reasons (strong
                 four-quadrant problems leave the scheme's stability region and diverge);
   comparator    the standard lattice Boltzmann comparator (Sec. I, Eq. 4) timed on the same
-                input, and the Galilean-invariance contrast measured on the GPU (shear-wave
-                viscosity in a moving frame, bump vs standard scheme);
+                input, the Galilean-invariance contrast measured on the GPU (shear-wave
+                viscosity in a moving frame, bump vs standard scheme), and the MRT step's
+                throughput beside the single-rate two-pass step;
   cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded sample (a 48^3
                 Taylor-Green vortex for ~10 s).
 
@@ -213,6 +214,27 @@ def run_standard(n, tau, mach, steps, warmup):
             "nonfinite_sites": health[0], "workload": f"Taylor-Green vortex {n}^3, Mach {mach}, tau {tau}, FP32"}
 
 
+def run_mrt(n, tau, mach, steps, warmup, tau_ghost=0.5):
+    """The multiple-relaxation-time step (non-hydrodynamic moments of Table I at their own rate;
+    two-pass kernel) beside the single-rate two-pass step, on the same Taylor-Green input."""
+    import torch
+    from paper_2501_00620_amd import lbm, workloads
+    rho, u, T = workloads.taylor_green(n, mach=mach)
+    out = {"tau_ghost": tau_ghost, "workload": f"Taylor-Green vortex {n}^3, Mach {mach}, tau {tau}, FP32, two-pass kernel"}
+    for name, tg in (("single_rate_mlups", None), ("mrt_mlups", tau_ghost)):
+        lat = lbm.Lattice(n, n, n, tau, storage="f32", kernel="two_pass")
+        if tg is not None:
+            lat.set_ghost_relaxation(tg)
+        lat.set_fields(rho, u, T)
+        secs = timed_steps(lat, steps, warmup)
+        out[name] = n ** 3 * steps / secs / 1e6
+        del lat
+        torch.cuda.empty_cache()
+    print(f"[bench] two-pass single rate {out['single_rate_mlups']:.0f}, MRT {out['mrt_mlups']:.0f} MLUPS",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def galilean_contrast(U=0.2, N=64, T0=1.0 / 3.0, tau=0.6, steps=2000, every=50):
     """The paper's Galilean-invariance contrast on the GPU: a shear wave u_y(x) on a background
     flow U along x decays with nu = T tau in the bump scheme and, by the standard scheme's third
@@ -365,7 +387,8 @@ def main():
         line["variants"] = run_variants(n, args.variant_steps, tau, mach)
         line["served"] = run_served_comparison(n_requests=args.serve_requests)
         line["comparator"] = {"standard": run_standard(n, tau, mach, args.steps, args.warmup),
-                              "galilean": galilean_contrast()}
+                              "galilean": galilean_contrast(),
+                              "mrt": run_mrt(n, tau, mach, args.steps, args.warmup)}
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     else:
         line["cpu_baseline"] = None
