@@ -19,6 +19,11 @@ Also reported on the same JSON line:
                 storage; p50/p99 time-to-result (per run and over the requests every storage
                 completed), aggregate MLUPS, failed requests with their reasons (strong
                 four-quadrant problems leave the scheme's stability region and diverge);
+  configs       the other workloads: the Sod tube (400 x 1 x 1, FP64) against the exact Riemann
+                solution at t = 75 and its invariants over 1000 steps; the 256^2 acoustic pulse
+                (FP32, 5000 steps), sound speeds of four Fourier modes against sqrt(5T/3) and
+                sqrt(T); 512^3 random smooth fields in FP16-deviation vs FP32 storage (500
+                steps): MLUPS, GB/s, relative L2;
   comparator    the standard lattice Boltzmann comparator (Sec. I, Eq. 4) timed on the same
                 input, the Galilean-invariance contrast measured on the GPU (shear-wave
                 viscosity in a moving frame, bump vs standard scheme), and the MRT step's
@@ -192,6 +197,111 @@ def run_served_comparison(storages=("f32", "f16dev", "bf16dev"), **kw):
         out[st]["common_requests"] = int(common.sum())
         out[st]["p50_s_common"] = float(np.percentile(lat[common], 50))
         out[st]["p99_s_common"] = float(np.percentile(lat[common], 99))
+    return out
+
+
+def _test_helpers():
+    """The tests' exact Riemann solution and damped-cosine fit (analysis, not the method)."""
+    path = os.path.join(ROOT, "tests")
+    if path not in sys.path:
+        sys.path.insert(0, path)
+    import fitting
+    import riemann
+    return fitting, riemann
+
+
+def run_sod(n=400, t_exact=75, steps=1000, tau=0.8):
+    """Shock tube on an n x 1 x 1 periodic D3Q19 lattice, FP64: the density at t = 75 (before the
+    periodic images interact) against the exact Riemann solution (gamma = 5/3), the invariants'
+    drift over the full 1000 steps, and the step rate."""
+    import numpy as np
+    from paper_2501_00620_amd import lbm, workloads
+    _, riemann = _test_helpers()
+    rho, u, T = workloads.sod(n, x0=n // 2)
+    lat = lbm.Lattice(n, 1, 1, tau, storage="f64")
+    lat.set_fields(rho, u, T)
+    i0 = lat.invariants()
+    lat.step(t_exact)
+    r = lat.moments()[0].cpu().numpy().reshape(n)
+    ex = riemann.RiemannSolution(1.0, 0.0, 1 / 3, 0.125, 0.0, 0.125 * 0.8 / 3, workloads.GAMMA)
+    x = np.arange(n, dtype=float)
+    re, _, _ = ex.profile(x, n / 2 - 0.5, float(t_exact))
+    win = (x >= 110) & (x < 320)
+    sp = ex.wave_speeds()
+    xc, xs = n / 2 - 0.5 + sp["contact"] * t_exact, n / 2 - 0.5 + sp["right_shock"] * t_exact
+    plateau_l = r[int(n / 2 - 0.5 + sp["left_tail"] * t_exact) + 4:int(xc) - 4].mean()
+    plateau_r = r[int(xc) + 5:int(xs) - 5].mean()
+    secs = timed_steps(lat, steps - t_exact, 0)
+    i1 = lat.invariants()
+    drift = np.abs((i1 - i0) / np.array([i0[0]] * 4 + [i0[4]])).max()
+    out = {"l1_rel_density_t75": float(np.abs(r - re)[win].mean() / re[win].mean()),
+           "plateau_left_rel_err": float(plateau_l / ex.rho_starL - 1),
+           "plateau_right_rel_err": float(plateau_r / ex.rho_starR - 1),
+           "invariant_drift_1000_steps": float(drift), "mlups": n * (steps - t_exact) / secs / 1e6,
+           "workload": f"Sod tube {n} x 1 x 1, FP64, tau {tau}, rho 1 | 0.125, T 1/3 | 0.8/3"}
+    print(f"[bench] Sod: L1 {out['l1_rel_density_t75']:.4f}, drift {drift:.1e}", file=sys.stderr, flush=True)
+    return out
+
+
+def run_acoustic(n=256, steps=5000, tau=0.6, every=4):
+    """Gaussian pulse on an n x n x 1 lattice, FP32: the sound speed of Fourier modes
+    k = 2 pi m / n (m = 1..4) fitted from the density's (m, 0) coefficient, against
+    sqrt(5 T / 3) (energy-conserving mode) and sqrt(T) (prescribed temperature)."""
+    import numpy as np
+    import torch
+    from paper_2501_00620_amd import lbm, workloads
+    fitting, _ = _test_helpers()
+    rho, u, T = workloads.acoustic_pulse(n)
+    T0 = float(T.flat[0])
+    out = {"workload": f"acoustic pulse {n}^2 x 1, FP32, tau {tau}, {steps} steps"}
+    for mode, c2 in (("thermal", 5.0 / 3.0 * T0), ("iso", T0)):
+        lat = lbm.Lattice(n, n, 1, tau, storage="f32", mode=mode)
+        lat.set_fields(rho, u, T)
+        ts, amps = [], []
+        for t in range(0, steps + 1, every):
+            if t:
+                lat.step(every)
+            r = lat.moments()[0].reshape(n, n).double()
+            amps.append(torch.fft.rfft(r.mean(dim=0) - 1.0)[1:5].real.cpu().numpy())
+            ts.append(t)
+        amps = np.array(amps)
+        ratios = []
+        for m in range(1, 5):
+            k = 2 * np.pi * m / n
+            w, g = fitting.fit_damped_cosine(ts, amps[:, m - 1], k, np.sqrt(c2), k * k * T0 * tau,
+                                             offset=(mode == "thermal"))
+            ratios.append(float((w * w + g * g) / (k * k) / c2))
+        out[mode] = {"cs2_over_predicted": ratios, "predicted_cs2": c2}
+        if mode == "thermal":
+            out["mlups"] = n * n * 1000 / timed_steps(lat, 1000, 0) / 1e6
+        del lat
+    print(f"[bench] acoustic: c_s^2 ratios thermal {out['thermal']['cs2_over_predicted']}, "
+          f"iso {out['iso']['cs2_over_predicted']}", file=sys.stderr, flush=True)
+    return out
+
+
+def run_large(n=512, steps=500, tau=0.6, seed=5):
+    """Random smooth fields on a 512^3 lattice in FP16-deviation storage, against the same run in
+    FP32 storage: MLUPS, achieved algorithmic GB/s, and the relative L2 error of rho, u, T."""
+    import torch
+    from paper_2501_00620_amd import lbm, workloads
+    rho, u, T = workloads.fourier_fields(n, n, n, seed=seed)
+    res, out = {}, {"workload": f"Fourier fields {n}^3, tau {tau}, {steps} steps"}
+    for storage in ("f32", "f16dev"):
+        lat = lbm.Lattice(n, n, n, tau, storage=storage)
+        lat.set_fields(rho, u, T)
+        secs = timed_steps(lat, steps, 5)
+        res[storage] = [x.double() for x in lat.moments()]
+        bpv = BYTES_PER_VALUE[storage]
+        out[storage] = {"mlups": n ** 3 * steps / secs / 1e6, "ms_per_step": secs * 1e3 / steps,
+                        "achieved_gbs": n ** 3 * VALUES_PER_LUP * bpv / (secs / steps) / 1e9,
+                        "nonfinite_sites": lat.health()[0]}
+        out[storage]["frac"] = out[storage]["achieved_gbs"] / HBM_PEAK_GBS
+        del lat
+        torch.cuda.empty_cache()
+    out["f16dev"]["rel_l2_vs_f32"] = {q: rel_l2(a, b) for q, a, b in zip(("rho", "u", "T"), res["f16dev"], res["f32"])}
+    print(f"[bench] 512^3: f32 {out['f32']['mlups']:.0f}, f16dev {out['f16dev']['mlups']:.0f} MLUPS",
+          file=sys.stderr, flush=True)
     return out
 
 
@@ -386,6 +496,7 @@ def main():
     if not args.quick:
         line["variants"] = run_variants(n, args.variant_steps, tau, mach)
         line["served"] = run_served_comparison(n_requests=args.serve_requests)
+        line["configs"] = {"sod": run_sod(), "acoustic": run_acoustic(), "large": run_large()}
         line["comparator"] = {"standard": run_standard(n, tau, mach, args.steps, args.warmup),
                               "galilean": galilean_contrast(),
                               "mrt": run_mrt(n, tau, mach, args.steps, args.warmup)}
