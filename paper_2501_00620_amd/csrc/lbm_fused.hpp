@@ -12,9 +12,11 @@
 //      populations, bbar and moments in registers for the next iteration;
 //   3. takes the isotropic gradients of plane z from the source planes z-1, z, z+1, collides
 //      the registers kept from the previous iteration, and pushes the results out.
-// Each site's populations are read from HBM once per step for its own update (plus the ring,
-// which neighbouring tiles on the same XCD usually bring into L2 at about the same time) and
-// written once: 2 x 25 values per lattice update, the algorithmic minimum.
+// The algorithmic minimum is 2 x 25 values per lattice update: each site's state read once and
+// written once.  On top of it come the ring sites (neighbouring tiles on the same XCD bring them
+// into L2 at about the same time) and the collision's second read of the tile's populations
+// (an L2 hit unless the stream in between evicted them).  The staging and source loads are
+// issued one plane iteration ahead of their use.
 //
 // Work-groups are numbered so that the ones dispatched to one XCD (block index mod 8) take
 // neighbouring tiles of the same z chunk, which share their rings through that XCD's L2.
