@@ -278,8 +278,12 @@ typedef struct {
     predictor p;
 } corrected;
 
-static void correct(int nx, int ny, int nz, double tau, int mode, const double *Tf, const double *F,
-                    const double *b, const double *src, int x, int y, int z, corrected *c)
+/* accel: a body-force acceleration field (3 planes) or NULL.  It enters the forcing moments in
+ * the manner of a Guo forcing: F += rho a, S += rho (u a + a u) with the corrected u, which then
+ * carries half of rho a as well (Eq. 57); the predictor sources stay force-free (as the paper
+ * keeps the uncorrected u there). */
+static void correct(int nx, int ny, int nz, double tau, int mode, const double *Tf, const double *accel,
+                    const double *F, const double *b, const double *src, int x, int y, int z, corrected *c)
 {
     const long n = (long)nx * ny * nz;
     const long s = site(nx, ny, x, y, z);
@@ -308,7 +312,14 @@ static void correct(int nx, int ny, int nz, double tau, int mode, const double *
         c->S[k] = -acc;
     }
     c->rho = c->p.rho;
+    if (accel)
+        for (int a = 0; a < 3; a++) c->Fv[a] += c->rho * accel[a * n + s];
     for (int a = 0; a < 3; a++) c->u[a] = (c->p.j[a] + 0.5 * c->Fv[a]) / c->rho; /* Eq. 57 */
+    if (accel)
+        for (int k = 0; k < NB; k++) {
+            const int bb = BA[k], g = BB[k];
+            c->S[k] += c->rho * (c->u[bb] * accel[g * n + s] + c->u[g] * accel[bb * n + s]);
+        }
     if (mode) {
         c->T = Tf[s];
     } else {
@@ -372,8 +383,8 @@ void orc_init(int nx, int ny, int nz, const double *rho, const double *u, const 
 /* nsteps full steps in place. mode 0 = energy-conserving temperature, 1 = prescribed T field.
  * tau_ghost: relaxation time of the non-hydrodynamic moments (rows 11-19 of Table I; see
  * collide); tau_ghost = tau is the single-relaxation-time scheme of the paper. */
-int orc_step_mrt(int nx, int ny, int nz, double tau, double tau_ghost, int mode, const double *Tf, double *F,
-                 double *b, long nsteps)
+int orc_step_ext(int nx, int ny, int nz, double tau, double tau_ghost, int mode, const double *Tf,
+                 const double *accel, double *F, double *b, long nsteps)
 {
     const long n = (long)nx * ny * nz;
     const double omega = 1.0 / (tau + 0.5);
@@ -395,7 +406,7 @@ int orc_step_mrt(int nx, int ny, int nz, double tau, double tau_ghost, int mode,
                 for (int x = 0; x < nx; x++) {
                     long s = site(nx, ny, x, y, z);
                     corrected c;
-                    correct(nx, ny, nz, tau, mode, Tf, F, b, src, x, y, z, &c);
+                    correct(nx, ny, nz, tau, mode, Tf, accel, F, b, src, x, y, z, &c);
                     double Fs[Q], bs[NB], Fo[Q], bo[NB];
                     for (int i = 0; i < Q; i++) Fs[i] = F[i * n + s];
                     for (int k = 0; k < NB; k++) bs[k] = b[k * n + s];
@@ -427,6 +438,13 @@ int orc_step_mrt(int nx, int ny, int nz, double tau, double tau_ghost, int mode,
     return 0;
 }
 
+/* The same without a body force. */
+int orc_step_mrt(int nx, int ny, int nz, double tau, double tau_ghost, int mode, const double *Tf, double *F,
+                 double *b, long nsteps)
+{
+    return orc_step_ext(nx, ny, nz, tau, tau_ghost, mode, Tf, NULL, F, b, nsteps);
+}
+
 /* nsteps single-relaxation-time steps (Eq. 55) in place. */
 int orc_step(int nx, int ny, int nz, double tau, int mode, const double *Tf, double *F, double *b,
              long nsteps)
@@ -435,8 +453,8 @@ int orc_step(int nx, int ny, int nz, double tau, int mode, const double *Tf, dou
 }
 
 /* Reported moments of the current state: rho, corrected u (3 planes), T (steps 1-3). */
-int orc_moments(int nx, int ny, int nz, double tau, int mode, const double *Tf, const double *F,
-                const double *b, double *rho, double *u, double *T)
+int orc_moments_ext(int nx, int ny, int nz, double tau, int mode, const double *Tf, const double *accel,
+                    const double *F, const double *b, double *rho, double *u, double *T)
 {
     const long n = (long)nx * ny * nz;
     double *src = malloc(sizeof(double) * NSRC * n);
@@ -448,7 +466,7 @@ int orc_moments(int nx, int ny, int nz, double tau, int mode, const double *Tf, 
             for (int x = 0; x < nx; x++) {
                 long s = site(nx, ny, x, y, z);
                 corrected c;
-                correct(nx, ny, nz, tau, mode, Tf, F, b, src, x, y, z, &c);
+                correct(nx, ny, nz, tau, mode, Tf, accel, F, b, src, x, y, z, &c);
                 rho[s] = c.rho;
                 for (int a = 0; a < 3; a++) u[a * n + s] = c.u[a];
                 T[s] = c.T;
@@ -458,6 +476,12 @@ int orc_moments(int nx, int ny, int nz, double tau, int mode, const double *Tf, 
 }
 
 /* Forcing moments F (3 planes) and S (6 planes) of the current state, for the tests. */
+int orc_moments(int nx, int ny, int nz, double tau, int mode, const double *Tf, const double *F,
+                const double *b, double *rho, double *u, double *T)
+{
+    return orc_moments_ext(nx, ny, nz, tau, mode, Tf, NULL, F, b, rho, u, T);
+}
+
 int orc_forcing_moments(int nx, int ny, int nz, double tau, int mode, const double *Tf,
                         const double *F, const double *b, double *Fv, double *S)
 {
@@ -471,7 +495,7 @@ int orc_forcing_moments(int nx, int ny, int nz, double tau, int mode, const doub
             for (int x = 0; x < nx; x++) {
                 long s = site(nx, ny, x, y, z);
                 corrected c;
-                correct(nx, ny, nz, tau, mode, Tf, F, b, src, x, y, z, &c);
+                correct(nx, ny, nz, tau, mode, Tf, NULL, F, b, src, x, y, z, &c);
                 for (int a = 0; a < 3; a++) Fv[a * n + s] = c.Fv[a];
                 for (int k = 0; k < NB; k++) S[k * n + s] = c.S[k];
             }
@@ -551,7 +575,7 @@ int orc_step_sites(int nx, int ny, int nz, double tau, int mode, const double *T
             int xu = 2 - E[i][0], yu = 2 - E[i][1], zu = 2 - E[i][2];
             long su = site(L, L, xu, yu, zu);
             corrected c;
-            correct(L, L, L, tau, mode, Tb, Fb, bb, src, xu, yu, zu, &c);
+            correct(L, L, L, tau, mode, Tb, NULL, Fb, bb, src, xu, yu, zu, &c);
             double Fs[Q], bs[NB], Fo[Q], bo[NB];
             for (int q = 0; q < Q; q++) Fs[q] = Fb[q * nb + su];
             for (int k = 0; k < NB; k++) bs[k] = bb[k * nb + su];

@@ -38,6 +38,10 @@ def _load():
         _lib.orc_step.restype = i
         _lib.orc_step_mrt.argtypes = [i, i, i, d, d, i, P, P, P, l]
         _lib.orc_step_mrt.restype = i
+        _lib.orc_step_ext.argtypes = [i, i, i, d, d, i, P, P, P, P, l]
+        _lib.orc_step_ext.restype = i
+        _lib.orc_moments_ext.argtypes = [i, i, i, d, i, P, P, P, P, P, P, P]
+        _lib.orc_moments_ext.restype = i
         _lib.orc_moments.argtypes = [i, i, i, d, i, P, P, P, P, P, P]
         _lib.orc_moments.restype = i
         _lib.orc_forcing_moments.argtypes = [i, i, i, d, i, P, P, P, P, P]
@@ -127,6 +131,7 @@ class OracleLattice:
         self.n = self.nx * self.ny * self.nz
         self.tau = float(tau)
         self.tau_ghost = self.tau if tau_ghost is None else float(tau_ghost)
+        self.accel = None  # body-force acceleration field (3, nz, ny, nx), or None
         self.mode = MODES[mode]
         shape = (self.nz, self.ny, self.nx)
         self.F = np.zeros((19,) + shape)
@@ -153,6 +158,14 @@ class OracleLattice:
             _load().orc_init(self.nx, self.ny, self.nz, _p(rho), _p(u), _p(T), _p(self.F), _p(self.b))
         self.steps = 0
 
+    def set_body_force(self, accel):
+        """Body-force acceleration field (3, nz, ny, nx) or a 3-vector; None removes it."""
+        if accel is None:
+            self.accel = None
+        else:
+            self.accel = _f64(np.broadcast_to(np.asarray(accel, dtype=np.float64).reshape(
+                (3,) + (1,) * 3 if np.size(accel) == 3 else (3,) + self.shape), (3,) + self.shape))
+
     def set_state(self, F, b):
         self.F = _f64(F).reshape((19,) + self.shape).copy()
         self.b = _f64(b).reshape((6,) + self.shape).copy()
@@ -164,8 +177,9 @@ class OracleLattice:
         if self.mode == 2:
             rc = _load().orc_step_std(self.nx, self.ny, self.nz, self.tau, _p(self.T_field), _p(self.F), int(n))
         else:
-            rc = _load().orc_step_mrt(self.nx, self.ny, self.nz, self.tau, self.tau_ghost, self.mode,
-                                      _p(self.T_field), _p(self.F), _p(self.b), int(n))
+            acc = None if self.accel is None else _p(self.accel)
+            rc = _load().orc_step_ext(self.nx, self.ny, self.nz, self.tau, self.tau_ghost, self.mode,
+                                      _p(self.T_field), acc, _p(self.F), _p(self.b), int(n))
         if rc != 0:
             raise MemoryError("oracle step failed")
         self.steps += int(n)
@@ -177,8 +191,9 @@ class OracleLattice:
         if self.mode == 2:
             _load().orc_moments_std(self.nx, self.ny, self.nz, _p(self.F), _p(rho), _p(u))
             return rho, u, self.T_field.copy()
-        rc = _load().orc_moments(self.nx, self.ny, self.nz, self.tau, self.mode, _p(self.T_field),
-                                 _p(self.F), _p(self.b), _p(rho), _p(u), _p(T))
+        acc = None if self.accel is None else _p(self.accel)
+        rc = _load().orc_moments_ext(self.nx, self.ny, self.nz, self.tau, self.mode, _p(self.T_field), acc,
+                                     _p(self.F), _p(self.b), _p(rho), _p(u), _p(T))
         if rc != 0:
             raise MemoryError("oracle moments failed")
         return rho, u, T
