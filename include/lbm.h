@@ -143,6 +143,15 @@ int lbm_set_kernel(lbm_handle h, int kernel);
  * non-finite, STANDARD mode, or the fused kernel forced by lbm_set_kernel). */
 int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost);
 
+/* Body-force acceleration field: 3n values of `dtype` (x, y, z planes, x fastest), or NULL to
+ * remove it.  It enters the forcing moments of Eqs. 58-61 as F += rho a and S += rho (u a + a u)
+ * with the corrected velocity of Eq. 57, which then carries half of rho a (a Guo-type forcing;
+ * the paper drives its Poiseuille and Couette flows with a body force, Sec. III A and C).  The
+ * field is copied (3 planes of the compute type on the device).  A lattice with a body force
+ * steps with the two-pass kernel.  Errors: ARG (dtype, STANDARD mode, fused kernel forced), OOM,
+ * HIP. */
+int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device);
+
 /* Block until all work queued on the lattice's stream is done. */
 int lbm_sync(lbm_handle h);
 void lbm_destroy(lbm_handle h);

@@ -180,15 +180,19 @@ template <int S> int step_two_pass(lbm_lattice *h) {
     if (h->gathered) {
         hipLaunchKernelGGL((k_predict<S, true>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k, h->codec);
         if (h->tau_ghost > 0.0)
-            hipLaunchKernelGGL((k_collide<S, true, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
+            hipLaunchKernelGGL((k_collide<S, true, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag,
+                               (const C *)h->accel);
         else
-            hipLaunchKernelGGL((k_collide<S, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
+            hipLaunchKernelGGL((k_collide<S, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag,
+                               (const C *)h->accel);
     } else {
         hipLaunchKernelGGL((k_predict<S, false>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k, h->codec);
         if (h->tau_ghost > 0.0)
-            hipLaunchKernelGGL((k_collide<S, false, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
+            hipLaunchKernelGGL((k_collide<S, false, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag,
+                               (const C *)h->accel);
         else
-            hipLaunchKernelGGL((k_collide<S, false>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag);
+            hipLaunchKernelGGL((k_collide<S, false>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag,
+                               (const C *)h->accel);
     }
     int rc = check_launch();
     if (rc) return rc;
@@ -231,7 +235,7 @@ template <int S> int step_std(lbm_lattice *h) {
 
 // the fused sweep relaxes with a single rate; a lattice with its own ghost rate steps two-pass
 bool use_fused(const lbm_lattice *h) {
-    return h->kernel != 1 && h->tau_ghost <= 0.0 && fused_supported(geo(h), h->p.storage);
+    return h->kernel != 1 && h->tau_ghost <= 0.0 && !h->accel && fused_supported(geo(h), h->p.storage);
 }
 
 }  // namespace
@@ -305,6 +309,7 @@ void lbm_destroy(lbm_handle h) {
         if (h->B[b]) (void)hipFree(h->B[b]);
     }
     if (h->src) (void)hipFree(h->src);
+    if (h->accel) (void)hipFree(h->accel);
     if (h->Tf) (void)hipFree(h->Tf);
     if (h->partial) (void)hipFree(h->partial);
     if (h->red_out) (void)hipFree(h->red_out);
@@ -318,8 +323,50 @@ int lbm_set_kernel(lbm_handle h, int kernel) {
         return fail(LBM_ERR_ARG, "fused sweep does not support this lattice shape");
     if (kernel == 2 && h->tau_ghost > 0.0)
         return fail(LBM_ERR_ARG, "the fused sweep relaxes with a single rate (a ghost rate is set)");
+    if (kernel == 2 && h->accel) return fail(LBM_ERR_ARG, "the fused sweep has no body force (one is set)");
     h->kernel = kernel;
     return LBM_OK;
+}
+
+int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (h->accel) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        (void)hipFree(h->accel);
+        h->accel = nullptr;
+    }
+    if (!accel) return LBM_OK;
+    if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_ARG, "unknown dtype %d", dtype);
+    if (h->p.mode == LBM_STANDARD) return fail(LBM_ERR_ARG, "the standard comparator has no body force");
+    if (h->kernel == 2) return fail(LBM_ERR_ARG, "the fused sweep has no body force (lbm_set_kernel chose it)");
+    const size_t count = 3 * (size_t)h->n, eb = dtype == LBM_DTYPE_F64 ? 8 : 4;
+    HIP_TRY(hipMalloc(&h->accel, compute_bytes(h->p.storage) * count));
+    void *stage = nullptr;
+    const void *src = accel;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&stage, eb * count));
+        hipError_t e = hipMemcpyAsync(stage, accel, eb * count, hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(stage);
+            return fail(LBM_ERR_HIP, "copy of the body force: %s", hipGetErrorString(e));
+        }
+        src = stage;
+    }
+    const unsigned blocks = (unsigned)((count + BLOCK - 1) / BLOCK);
+    int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
+        using C = typename Storage<decltype(SI)::value>::C;
+        if (dtype == LBM_DTYPE_F64)
+            hipLaunchKernelGGL((k_cast<double, C>), dim3(blocks), dim3(BLOCK), 0, h->stream, (const double *)src,
+                               (C *)h->accel, count);
+        else
+            hipLaunchKernelGGL((k_cast<float, C>), dim3(blocks), dim3(BLOCK), 0, h->stream, (const float *)src,
+                               (C *)h->accel, count);
+        return check_launch();
+    });
+    const hipError_t e = hipStreamSynchronize(h->stream);
+    if (stage) (void)hipFree(stage);
+    if (!rc && e != hipSuccess) rc = fail(LBM_ERR_HIP, "body force: %s", hipGetErrorString(e));
+    return rc;
 }
 
 int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost) {
@@ -507,7 +554,7 @@ int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on
             }
             hipLaunchKernelGGL((k_predict<S, G>), grid, block, 0, h->stream, F, B, src, (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
             hipLaunchKernelGGL((k_readout<S, G, OUT>), grid, block, 0, h->stream, F, B, (const C *)src, (const C *)h->Tf,
-                               (C)h->Tconst, g, k, h->codec, h->p.T_ref, (OUT *)dr, (OUT *)du, (OUT *)dT);
+                               (C)h->Tconst, g, k, h->codec, h->p.T_ref, (OUT *)dr, (OUT *)du, (OUT *)dT, (const C *)h->accel);
         };
         struct D { using type = double; };
         struct Fl { using type = float; };

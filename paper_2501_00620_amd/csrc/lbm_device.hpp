@@ -316,6 +316,25 @@ __device__ __forceinline__ void grad_finish_thin(const GradAcc<C> &g, C F[3], C 
     for (int c = 3; c < 6; c++) S[c] = -(g.fS[c] * C(1.0 / 3.0) + g.eS[c] * C(1.0 / 12.0));
 }
 
+// A body-force acceleration a in the forcing moments, in the manner of a Guo forcing:
+// F += rho a and S += rho (u a + a u), u the corrected velocity of Eq. 57 (which, formed from the
+// new F by collide, carries half of rho a).
+template <typename C>
+__device__ __forceinline__ void add_body_force(const PopMoments<C> &m, const C a[3], C F[3], C S[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) F[c] = fma(m.rho, a[c], F[c]);
+    const C inv = recip(m.rho);
+    const C ux = (m.jx + C(0.5) * F[0]) * inv;  // as collide forms it
+    const C uy = (m.jy + C(0.5) * F[1]) * inv;
+    const C uz = (m.jz + C(0.5) * F[2]) * inv;
+    S[0] = fma(C(2) * m.rho, ux * a[0], S[0]);
+    S[1] = fma(C(2) * m.rho, uy * a[1], S[1]);
+    S[2] = fma(C(2) * m.rho, uz * a[2], S[2]);
+    S[3] = fma(m.rho, fma(ux, a[1], uy * a[0]), S[3]);
+    S[4] = fma(m.rho, fma(ux, a[2], uz * a[0]), S[4]);
+    S[5] = fma(m.rho, fma(uy, a[2], uz * a[1]), S[5]);
+}
+
 // Steps 3-5: corrected moments, equilibria, forcing and the BGK update, in place on the
 // deviations d and beta.  Returns the corrected u and theta = T - T_ref if asked.
 //

@@ -27,6 +27,7 @@ struct lbm_lattice {
     int kernel = 0;
     int slots = 256;            // fused work-groups resident at once (one per CU)
     double tau_ghost = -1.0;    // relaxation time of Table I rows 11-19 (<= 0: the single rate)
+    void *accel = nullptr;      // body-force acceleration, 3 planes of the compute type, or null
 };
 
 namespace lbm {

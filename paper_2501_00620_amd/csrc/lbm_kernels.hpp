@@ -116,7 +116,7 @@ k_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S
           const typename Storage<S>::C *__restrict__ src, typename Storage<S>::T *__restrict__ Fo,
           typename Storage<S>::T *__restrict__ Bo, const typename Storage<S>::C *__restrict__ Tf,
           typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd,
-          unsigned *__restrict__ flag) {
+          unsigned *__restrict__ flag, const typename Storage<S>::C *__restrict__ accel) {
     using C = typename Storage<S>::C;
     const int s = blockIdx.x * BLOCK + threadIdx.x;
     if (s >= g.n) return;
@@ -128,6 +128,10 @@ k_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S
     load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, f, bbar, m);
     C Fv[3], Sv[6];
     gradient_from_src(src, g.n, nb, k.K, Fv, Sv);
+    if (accel) {  // body force (uniform branch: one field for the whole lattice)
+        const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
+        add_body_force(m, a, Fv, Sv);
+    }
     C f0[MRT ? Q : 1];
     if constexpr (MRT) {
 #pragma unroll
@@ -150,7 +154,8 @@ __global__ void __launch_bounds__(BLOCK)
 k_readout(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
           const typename Storage<S>::C *__restrict__ src, const typename Storage<S>::C *__restrict__ Tf,
           typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd, double T_ref,
-          OUT *__restrict__ rho, OUT *__restrict__ u, OUT *__restrict__ T) {
+          OUT *__restrict__ rho, OUT *__restrict__ u, OUT *__restrict__ T,
+          const typename Storage<S>::C *__restrict__ accel) {
     using C = typename Storage<S>::C;
     const int s = blockIdx.x * BLOCK + threadIdx.x;
     if (s >= g.n) return;
@@ -162,6 +167,10 @@ k_readout(const typename Storage<S>::T *__restrict__ F, const typename Storage<S
     load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, f, bbar, m);
     C Fv[3], Sv[6];
     gradient_from_src(src, g.n, nb, k.K, Fv, Sv);
+    if (accel) {
+        const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
+        add_body_force(m, a, Fv, Sv);
+    }
     C uc[3], Tc;
     collide(f, bbar, m, Fv, Sv, site_T(Tf, Tconst, s), k, uc, &Tc);
     if (rho) rho[s] = (OUT)((double)k.rho_ref + (double)m.drho);
@@ -195,6 +204,13 @@ k_init(const IN *__restrict__ rho, const IN *__restrict__ u, const IN *__restric
     for (int c = 0; c < NB; c++) Storage<S>::store(B, (size_t)c * n + s, Q + c, (C)b[c], cd, sat);
     if (Tf) Tf[s] = (C)theta;
     if (sat) *flag = 1u;
+}
+
+// ---- conversion of a caller's field to the compute type ------------------------------------------
+template <typename IN, typename C>
+__global__ void __launch_bounds__(BLOCK) k_cast(const IN *__restrict__ in, C *__restrict__ out, size_t count) {
+    const size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < count) out[i] = (C)in[i];
 }
 
 // ---- standard lattice Boltzmann comparator (Sec. I, Eq. 4) ---------------------------------------

@@ -51,6 +51,7 @@ SIGNATURES = {
     "lbm_health": ([C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_double)], C.c_int),
     "lbm_set_kernel": ([C.c_void_p, C.c_int], C.c_int),
     "lbm_set_ghost_relaxation": ([C.c_void_p, C.c_double], C.c_int),
+    "lbm_set_body_force": ([C.c_void_p, C.c_void_p, C.c_int, C.c_int], C.c_int),
     "lbm_sync": ([C.c_void_p], C.c_int),
     "lbm_destroy": ([C.c_void_p], None),
     "lbm_last_error": ([], C.c_char_p),
@@ -163,6 +164,17 @@ class Lattice:
 
     def set_kernel(self, kernel):
         _check(_lib.lbm_set_kernel(self._h, KERNEL[kernel] if isinstance(kernel, str) else int(kernel)))
+
+    def set_body_force(self, accel):
+        """Body-force acceleration: an array (3, nz, ny, nx), a 3-vector (uniform), or None to
+        remove it.  Such a lattice steps with the two-pass kernel."""
+        if accel is None:
+            _check(_lib.lbm_set_body_force(self._h, None, 0, 0))
+            return
+        a = np.asarray(accel, dtype=np.float64)
+        shape = (3, self.nz, self.ny, self.nx)
+        a = np.ascontiguousarray(np.broadcast_to(a.reshape(3, 1, 1, 1) if a.size == 3 else a, shape))
+        _check(_lib.lbm_set_body_force(self._h, a.ctypes.data_as(C.c_void_p), 0, 0))
 
     def set_ghost_relaxation(self, tau_ghost):
         """Relaxation time of the non-hydrodynamic moments (Table I rows 11-19); tau_ghost = tau
