@@ -26,8 +26,9 @@ Also reported on the same JSON line:
                 steps): MLUPS, GB/s, relative L2;
   comparator    the standard lattice Boltzmann comparator (Sec. I, Eq. 4) timed on the same
                 input, the Galilean-invariance contrast measured on the GPU (shear-wave
-                viscosity in a moving frame, bump vs standard scheme), and the MRT step's
-                throughput beside the single-rate two-pass step;
+                viscosity in a moving frame, bump vs standard scheme), the MRT step's
+                throughput beside the single-rate two-pass step, and the body force (two-pass
+                throughput; Kolmogorov-flow amplitude against A / (T tau k^2));
   cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded sample (a 48^3
                 Taylor-Green vortex for ~10 s).
 
@@ -345,6 +346,37 @@ def run_mrt(n, tau, mach, steps, warmup, tau_ghost=0.5):
     return out
 
 
+def body_force(n=256, tau=0.55, mach=0.5, steps=100, N=64, T0=0.2, tau_k=0.6, A=1e-6, k_steps=8000):
+    """Body force: the two-pass step with an acceleration field on the Taylor-Green input, and the
+    Kolmogorov flow a_y = A sin(kx) on the GPU, whose steady amplitude is A / (T tau k^2)."""
+    import numpy as np
+    import torch
+    from paper_2501_00620_amd import lbm, workloads
+    rho, u, T = workloads.taylor_green(n, mach=mach)
+    lat = lbm.Lattice(n, n, n, tau, storage="f32")
+    lat.set_fields(rho, u, T)
+    lat.set_body_force([0.0, 1e-5, 0.0])
+    secs = timed_steps(lat, steps, 5)
+    out = {"two_pass_mlups": n ** 3 * steps / secs / 1e6,
+           "workload": f"Taylor-Green vortex {n}^3 FP32 with a uniform acceleration; Kolmogorov flow {N} x 1 x 1, "
+                       f"T {T0}, tau {tau_k}, {k_steps} steps"}
+    del lat
+    torch.cuda.empty_cache()
+    k = 2 * np.pi / N
+    x = np.arange(N)
+    g = lbm.Lattice(N, 1, 1, tau_k, storage="f64", mode="iso")
+    g.set_fields(np.ones((1, 1, N)), np.zeros((3, 1, 1, N)), np.full((1, 1, N), T0))
+    accel = np.zeros((3, 1, 1, N))
+    accel[1, 0, 0] = A * np.sin(k * x)
+    g.set_body_force(accel)
+    g.step(k_steps)
+    uy = g.moments()[1][1].cpu().numpy().reshape(N)
+    out["kolmogorov_amplitude_over_predicted"] = float(2.0 / N * np.sum(uy * np.sin(k * x)) / (A / (T0 * tau_k * k * k)))
+    print(f"[bench] body force: two-pass {out['two_pass_mlups']:.0f} MLUPS, Kolmogorov amplitude ratio "
+          f"{out['kolmogorov_amplitude_over_predicted']:.4f}", file=sys.stderr, flush=True)
+    return out
+
+
 def galilean_contrast(U=0.2, N=64, T0=1.0 / 3.0, tau=0.6, steps=2000, every=50):
     """The paper's Galilean-invariance contrast on the GPU: a shear wave u_y(x) on a background
     flow U along x decays with nu = T tau in the bump scheme and, by the standard scheme's third
@@ -499,7 +531,8 @@ def main():
         line["configs"] = {"sod": run_sod(), "acoustic": run_acoustic(), "large": run_large()}
         line["comparator"] = {"standard": run_standard(n, tau, mach, args.steps, args.warmup),
                               "galilean": galilean_contrast(),
-                              "mrt": run_mrt(n, tau, mach, args.steps, args.warmup)}
+                              "mrt": run_mrt(n, tau, mach, args.steps, args.warmup),
+                              "body_force": body_force()}
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     else:
         line["cpu_baseline"] = None
