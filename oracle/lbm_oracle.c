@@ -35,6 +35,23 @@
  * The readings behind steps 1, 3, 6 (temperature closure, which velocity enters the gradient
  * sources, post-collision gather weights, the D3Q19 finite-difference stencil) are listed with
  * their reasons in the design notes of the repository.
+ *
+ * Walls (the channels of Sec. III A and C): optionally two planar walls normal to z, half-way
+ * between the last fluid plane and its periodic image (z = -1/2 and z = nz - 1/2), with
+ * tangential velocities u_b (bottom) and u_t (top); x and y stay periodic.  Read as follows:
+ *   - half-way bounce-back with the moving-wall momentum of Ladd: a population that would stream
+ *     through a wall returns to its site reversed, plus 6 w_i rho(x) e_i.u_w, which is
+ *     feq_i(rho, u_w) - feq_opp(i)(rho, u_w) of Appendix A (its odd part is exactly linear in u);
+ *   - it carries the variance of the site it left, which is also its destination (a full reversal
+ *     maps a second moment onto itself);
+ *   - the gradient sources one plane beyond a wall, in the same (x, y) column:
+ *       R = rho b (the variance part of the pressure) is mirrored, R(-1) = R(0), as bounce-back
+ *       mirrors the populations' own second moment (a reversal maps a second moment onto itself);
+ *       X = rho u* b is extrapolated to second order, X(-1) = 3 X(0) - 3 X(1) + X(2), so its
+ *       z-derivative at a wall-adjacent site is the one-sided second-order difference.
+ *     Extrapolating R as well destabilises the energy-conserving mode below T = 1/3 and moving
+ *     walls under gravity; mirroring X spoils the viscous stress at a no-slip wall and the
+ *     hydrostatic balance (u* carries half the body force).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -196,6 +213,42 @@ static void neighbours(int nx, int ny, int nz, int x, int y, int z, long *nbr)
         nbr[i] = site(nx, ny, wrap(x + E[i][0], nx), wrap(y + E[i][1], ny), wrap(z + E[i][2], nz));
 }
 
+/* Index of the velocity -e_i. */
+static int opp(int i)
+{
+    for (int j = 0; j < Q; j++)
+        if (E[j][0] == -E[i][0] && E[j][1] == -E[i][1] && E[j][2] == -E[i][2]) return j;
+    return -1;
+}
+
+/* phi at (x, y, z) with x, y periodic and z either periodic (walls = 0) or bounded by the two
+ * walls (walls = 1): one plane beyond a wall is the mirror image of the wall-adjacent plane
+ * (extrap = 0) or extrapolated from the three planes inside it (extrap = 1). */
+static double value_at(const double *phi, int nx, int ny, int nz, int walls, int extrap, int x, int y, int z)
+{
+    x = wrap(x, nx);
+    y = wrap(y, ny);
+    if (!walls) return phi[site(nx, ny, x, y, wrap(z, nz))];
+    if (z < 0 || z >= nz) {
+        const int z0 = z < 0 ? 0 : nz - 1, d = z < 0 ? 1 : -1;
+        const double p0 = phi[site(nx, ny, x, y, z0)];
+        if (!extrap) return p0;
+        return 3.0 * p0 - 3.0 * phi[site(nx, ny, x, y, z0 + d)] + phi[site(nx, ny, x, y, z0 + 2 * d)];
+    }
+    return phi[site(nx, ny, x, y, z)];
+}
+
+/* The stencil below with the neighbour values from value_at (used when walls bound z). */
+static double fd_walls(const double *phi, int nx, int ny, int nz, int extrap, int x, int y, int z, int a)
+{
+    double s = 0.0;
+    for (int i = 1; i < Q; i++) {
+        if (E[i][a] == 0) continue;
+        s += W[i] * E[i][a] * value_at(phi, nx, ny, nz, 1, extrap, x + E[i][0], y + E[i][1], z + E[i][2]);
+    }
+    return 3.0 * s;
+}
+
 /* Isotropic finite difference d_a phi(x) = (1/cs^2) sum_i w_i e_ia phi(x + e_i), cs^2 = 1/3,
  * over the 18 D3Q19 neighbours (nbr from neighbours()). */
 static double fd(const double *phi, const long *nbr, int a)
@@ -283,7 +336,8 @@ typedef struct {
  * carries half of rho a as well (Eq. 57); the predictor sources stay force-free (as the paper
  * keeps the uncorrected u there). */
 static void correct(int nx, int ny, int nz, double tau, int mode, const double *Tf, const double *accel,
-                    const double *F, const double *b, const double *src, int x, int y, int z, corrected *c)
+                    int walls, const double *F, const double *b, const double *src, int x, int y, int z,
+                    corrected *c)
 {
     const long n = (long)nx * ny * nz;
     const long s = site(nx, ny, x, y, z);
@@ -294,11 +348,13 @@ static void correct(int nx, int ny, int nz, double tau, int mode, const double *
     predict(Fs, bs, mode ? Tf[s] : 0.0, mode, omega, &c->p);
     long nbr[Q];
     neighbours(nx, ny, nz, x, y, z, nbr);
+#define D(plane, a) (walls ? fd_walls(src + (long)(plane) * n, nx, ny, nz, (plane) >= NB, x, y, z, a) \
+                           : fd(src + (long)(plane) * n, nbr, a))
 
     /* F_b = - d_a (rho b_ab)  (Eq. 59) */
     for (int bb = 0; bb < 3; bb++) {
         double acc = 0.0;
-        for (int a = 0; a < 3; a++) acc += fd(src + (long)comp(a, bb) * n, nbr, a);
+        for (int a = 0; a < 3; a++) acc += D(comp(a, bb), a);
         c->Fv[bb] = -acc;
     }
     /* S_bg = - d_a (rho u_g b_ab + rho u_b b_ga)  (Eq. 61) */
@@ -306,11 +362,12 @@ static void correct(int nx, int ny, int nz, double tau, int mode, const double *
         int bb = BA[k], g = BB[k];
         double acc = 0.0;
         for (int a = 0; a < 3; a++) {
-            acc += fd(src + (long)(NB + 3 * comp(a, bb) + g) * n, nbr, a);
-            acc += fd(src + (long)(NB + 3 * comp(g, a) + bb) * n, nbr, a);
+            acc += D(NB + 3 * comp(a, bb) + g, a);
+            acc += D(NB + 3 * comp(g, a) + bb, a);
         }
         c->S[k] = -acc;
     }
+#undef D
     c->rho = c->p.rho;
     if (accel)
         for (int a = 0; a < 3; a++) c->Fv[a] += c->rho * accel[a * n + s];
@@ -380,22 +437,33 @@ void orc_init(int nx, int ny, int nz, const double *rho, const double *u, const 
     }
 }
 
+/* Wall velocities uw = (u_b, u_t) must be tangential, and the extrapolation needs 3 planes. */
+static int walls_invalid(int nz, const double *uw)
+{
+    return uw && (nz < 3 || uw[2] != 0.0 || uw[5] != 0.0);
+}
+
 /* nsteps full steps in place. mode 0 = energy-conserving temperature, 1 = prescribed T field.
  * tau_ghost: relaxation time of the non-hydrodynamic moments (rows 11-19 of Table I; see
- * collide); tau_ghost = tau is the single-relaxation-time scheme of the paper. */
-int orc_step_ext(int nx, int ny, int nz, double tau, double tau_ghost, int mode, const double *Tf,
-                 const double *accel, double *F, double *b, long nsteps)
+ * collide); tau_ghost = tau is the single-relaxation-time scheme of the paper.
+ * uw: NULL (periodic in z) or the bottom and top wall velocities (6 values; see the header). */
+int orc_step_walls(int nx, int ny, int nz, double tau, double tau_ghost, int mode, const double *Tf,
+                   const double *accel, const double *uw, double *F, double *b, long nsteps)
 {
     const long n = (long)nx * ny * nz;
     const double omega = 1.0 / (tau + 0.5);
     const double omega_g = tau_ghost == tau ? omega : 1.0 / (tau_ghost + 0.5);
+    const int walls = uw != NULL;
+    if (walls_invalid(nz, uw)) return -3;
     double *src = malloc(sizeof(double) * NSRC * n);
     double *Fp = malloc(sizeof(double) * Q * n);
     double *bp = malloc(sizeof(double) * NB * n);
-    if (!src || !Fp || !bp) {
+    double *rp = malloc(sizeof(double) * n);
+    if (!src || !Fp || !bp || !rp) {
         free(src);
         free(Fp);
         free(bp);
+        free(rp);
         return -1;
     }
     for (long it = 0; it < nsteps; it++) {
@@ -406,13 +474,14 @@ int orc_step_ext(int nx, int ny, int nz, double tau, double tau_ghost, int mode,
                 for (int x = 0; x < nx; x++) {
                     long s = site(nx, ny, x, y, z);
                     corrected c;
-                    correct(nx, ny, nz, tau, mode, Tf, accel, F, b, src, x, y, z, &c);
+                    correct(nx, ny, nz, tau, mode, Tf, accel, walls, F, b, src, x, y, z, &c);
                     double Fs[Q], bs[NB], Fo[Q], bo[NB];
                     for (int i = 0; i < Q; i++) Fs[i] = F[i * n + s];
                     for (int k = 0; k < NB; k++) bs[k] = b[k * n + s];
                     collide(Fs, bs, &c, omega, omega_g, Fo, bo);
                     for (int i = 0; i < Q; i++) Fp[i * n + s] = Fo[i];
                     for (int k = 0; k < NB; k++) bp[k * n + s] = bo[k];
+                    rp[s] = c.rho;
                 }
         /* step 6: stream and gather */
 #pragma omp parallel for schedule(static)
@@ -422,9 +491,19 @@ int orc_step_ext(int nx, int ny, int nz, double tau, double tau_ghost, int mode,
                     long s = site(nx, ny, x, y, z);
                     double rho = 0.0, acc[NB] = {0, 0, 0, 0, 0, 0};
                     for (int i = 0; i < Q; i++) {
-                        long from = site(nx, ny, wrap(x - E[i][0], nx), wrap(y - E[i][1], ny),
-                                         wrap(z - E[i][2], nz));
-                        double fi = Fp[i * n + from];
+                        const int zf = z - E[i][2];
+                        long from;
+                        double fi;
+                        if (walls && (zf < 0 || zf >= nz)) {
+                            /* bounce-back: the population that left x towards the wall */
+                            const double *u_w = zf < 0 ? uw : uw + 3;
+                            from = s;
+                            fi = Fp[opp(i) * n + s] +
+                                 6.0 * W[i] * rp[s] * (E[i][0] * u_w[0] + E[i][1] * u_w[1] + E[i][2] * u_w[2]);
+                        } else {
+                            from = site(nx, ny, wrap(x - E[i][0], nx), wrap(y - E[i][1], ny), wrap(zf, nz));
+                            fi = Fp[i * n + from];
+                        }
                         F[i * n + s] = fi;
                         rho += fi;
                         for (int k = 0; k < NB; k++) acc[k] += fi * bp[k * n + from];
@@ -435,7 +514,15 @@ int orc_step_ext(int nx, int ny, int nz, double tau, double tau_ghost, int mode,
     free(src);
     free(Fp);
     free(bp);
+    free(rp);
     return 0;
+}
+
+/* Periodic in all three directions. */
+int orc_step_ext(int nx, int ny, int nz, double tau, double tau_ghost, int mode, const double *Tf,
+                 const double *accel, double *F, double *b, long nsteps)
+{
+    return orc_step_walls(nx, ny, nz, tau, tau_ghost, mode, Tf, accel, NULL, F, b, nsteps);
 }
 
 /* The same without a body force. */
@@ -452,11 +539,13 @@ int orc_step(int nx, int ny, int nz, double tau, int mode, const double *Tf, dou
     return orc_step_mrt(nx, ny, nz, tau, tau, mode, Tf, F, b, nsteps);
 }
 
-/* Reported moments of the current state: rho, corrected u (3 planes), T (steps 1-3). */
-int orc_moments_ext(int nx, int ny, int nz, double tau, int mode, const double *Tf, const double *accel,
-                    const double *F, const double *b, double *rho, double *u, double *T)
+/* Reported moments of the current state: rho, corrected u (3 planes), T (steps 1-3).
+ * walls: nonzero when walls bound z (only the gradient stencil depends on it). */
+int orc_moments_walls(int nx, int ny, int nz, double tau, int mode, const double *Tf, const double *accel,
+                      int walls, const double *F, const double *b, double *rho, double *u, double *T)
 {
     const long n = (long)nx * ny * nz;
+    if (walls && nz < 3) return -3;
     double *src = malloc(sizeof(double) * NSRC * n);
     if (!src) return -1;
     sources(nx, ny, nz, tau, mode, Tf, F, b, src);
@@ -466,7 +555,7 @@ int orc_moments_ext(int nx, int ny, int nz, double tau, int mode, const double *
             for (int x = 0; x < nx; x++) {
                 long s = site(nx, ny, x, y, z);
                 corrected c;
-                correct(nx, ny, nz, tau, mode, Tf, accel, F, b, src, x, y, z, &c);
+                correct(nx, ny, nz, tau, mode, Tf, accel, walls, F, b, src, x, y, z, &c);
                 rho[s] = c.rho;
                 for (int a = 0; a < 3; a++) u[a * n + s] = c.u[a];
                 T[s] = c.T;
@@ -475,13 +564,19 @@ int orc_moments_ext(int nx, int ny, int nz, double tau, int mode, const double *
     return 0;
 }
 
-/* Forcing moments F (3 planes) and S (6 planes) of the current state, for the tests. */
+int orc_moments_ext(int nx, int ny, int nz, double tau, int mode, const double *Tf, const double *accel,
+                    const double *F, const double *b, double *rho, double *u, double *T)
+{
+    return orc_moments_walls(nx, ny, nz, tau, mode, Tf, accel, 0, F, b, rho, u, T);
+}
+
 int orc_moments(int nx, int ny, int nz, double tau, int mode, const double *Tf, const double *F,
                 const double *b, double *rho, double *u, double *T)
 {
     return orc_moments_ext(nx, ny, nz, tau, mode, Tf, NULL, F, b, rho, u, T);
 }
 
+/* Forcing moments F (3 planes) and S (6 planes) of the current state, for the tests. */
 int orc_forcing_moments(int nx, int ny, int nz, double tau, int mode, const double *Tf,
                         const double *F, const double *b, double *Fv, double *S)
 {
@@ -495,7 +590,7 @@ int orc_forcing_moments(int nx, int ny, int nz, double tau, int mode, const doub
             for (int x = 0; x < nx; x++) {
                 long s = site(nx, ny, x, y, z);
                 corrected c;
-                correct(nx, ny, nz, tau, mode, Tf, NULL, F, b, src, x, y, z, &c);
+                correct(nx, ny, nz, tau, mode, Tf, NULL, 0, F, b, src, x, y, z, &c);
                 for (int a = 0; a < 3; a++) Fv[a * n + s] = c.Fv[a];
                 for (int k = 0; k < NB; k++) S[k * n + s] = c.S[k];
             }
@@ -575,7 +670,7 @@ int orc_step_sites(int nx, int ny, int nz, double tau, int mode, const double *T
             int xu = 2 - E[i][0], yu = 2 - E[i][1], zu = 2 - E[i][2];
             long su = site(L, L, xu, yu, zu);
             corrected c;
-            correct(L, L, L, tau, mode, Tb, NULL, Fb, bb, src, xu, yu, zu, &c);
+            correct(L, L, L, tau, mode, Tb, NULL, 0, Fb, bb, src, xu, yu, zu, &c);
             double Fs[Q], bs[NB], Fo[Q], bo[NB];
             for (int q = 0; q < Q; q++) Fs[q] = Fb[q * nb + su];
             for (int k = 0; k < NB; k++) bs[k] = bb[k * nb + su];
@@ -603,8 +698,12 @@ int orc_step_sites(int nx, int ny, int nz, double tau, int mode, const double *T
  * offset is T - 1/3):
  *     feq_i = rho w_i [1 + 3 e_i.u + 9/2 (u_a u_b + (T - 1/3) delta_ab)(e_ia e_ib - delta_ab/3)].
  * The paper uses it as the contrast to the bump scheme in the Galilean-invariance experiment of
- * Sec. III C.  One step: BGK with the same relaxation factor omega = 1/(tau + 1/2) (Eq. 55
- * without forcing), then streaming; T is a prescribed field.
+ * Sec. III C.  One step: BGK with the same relaxation factor omega = 1/(tau + 1/2) (Eq. 55),
+ * then streaming; T is a prescribed field.  A body force enters as in the bump scheme: the
+ * forcing Phi built from F = rho a and S = rho (u a + a u) (orc_forcing), weighted by
+ * 1 - omega/2, with u = (j + F/2)/rho; there is no gradient forcing (no variance).  The walls
+ * are those of the bump scheme (half-way bounce-back with the moving-wall momentum
+ * 6 w_i rho e_i.u_w, which is also the odd part of this equilibrium).
  * ------------------------------------------------------------------------------------------- */
 void orc_feq_std(double rho, double ux, double uy, double uz, double T, double *f)
 {
@@ -631,49 +730,93 @@ void orc_init_std(int nx, int ny, int nz, const double *rho, const double *u, co
     }
 }
 
-int orc_step_std(int nx, int ny, int nz, double tau, const double *Tf, double *F, long nsteps)
+/* Velocity of the standard model at one site: (j + rho a / 2) / rho, a = accel or none. */
+static void std_velocity(const double *Fsite, const double *a, double *rho, double *u)
+{
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; i++) {
+        r += Fsite[i];
+        for (int c = 0; c < 3; c++) j[c] += Fsite[i] * E[i][c];
+    }
+    *rho = r;
+    for (int c = 0; c < 3; c++) u[c] = (j[c] + (a ? 0.5 * r * a[c] : 0.0)) / r;
+}
+
+int orc_step_std_walls(int nx, int ny, int nz, double tau, const double *Tf, const double *accel,
+                       const double *uw, double *F, long nsteps)
 {
     const long n = (long)nx * ny * nz;
     const double omega = 1.0 / (tau + 0.5);
+    const int walls = uw != NULL;
+    if (uw && (uw[2] != 0.0 || uw[5] != 0.0)) return -3;
     double *Fp = malloc(sizeof(double) * Q * n);
-    if (!Fp) return -1;
+    double *rp = malloc(sizeof(double) * n);
+    if (!Fp || !rp) {
+        free(Fp);
+        free(rp);
+        return -1;
+    }
     for (long it = 0; it < nsteps; it++) {
+#pragma omp parallel for schedule(static)
+        for (long s = 0; s < n; s++) {
+            double Fs[Q], a[3], rho, u[3], feq[Q], phi[Q];
+            for (int i = 0; i < Q; i++) Fs[i] = F[i * n + s];
+            if (accel)
+                for (int c = 0; c < 3; c++) a[c] = accel[c * n + s];
+            std_velocity(Fs, accel ? a : NULL, &rho, u);
+            orc_feq_std(rho, u[0], u[1], u[2], Tf[s], feq);
+            for (int i = 0; i < Q; i++) phi[i] = 0.0;
+            if (accel) {
+                const double Fv[3] = {rho * a[0], rho * a[1], rho * a[2]};
+                double S[NB];
+                for (int k = 0; k < NB; k++) S[k] = rho * (u[BA[k]] * a[BB[k]] + u[BB[k]] * a[BA[k]]);
+                orc_forcing(Fv, S, phi);
+            }
+            for (int i = 0; i < Q; i++) Fp[i * n + s] = Fs[i] - omega * (Fs[i] - feq[i]) + (1.0 - 0.5 * omega) * phi[i];
+            rp[s] = rho;
+        }
 #pragma omp parallel for schedule(static)
         for (int z = 0; z < nz; z++)
             for (int y = 0; y < ny; y++)
                 for (int x = 0; x < nx; x++) {
                     const long s = site(nx, ny, x, y, z);
-                    double rho = 0.0, j[3] = {0.0, 0.0, 0.0}, feq[Q];
                     for (int i = 0; i < Q; i++) {
-                        const double fi = F[i * n + s];
-                        rho += fi;
-                        for (int a = 0; a < 3; a++) j[a] += fi * E[i][a];
-                    }
-                    orc_feq_std(rho, j[0] / rho, j[1] / rho, j[2] / rho, Tf[s], feq);
-                    for (int i = 0; i < Q; i++) {
-                        const double fi = F[i * n + s];
-                        const long to = site(nx, ny, wrap(x + E[i][0], nx), wrap(y + E[i][1], ny),
-                                             wrap(z + E[i][2], nz));
-                        Fp[i * n + to] = fi - omega * (fi - feq[i]);
+                        const int zf = z - E[i][2];
+                        if (walls && (zf < 0 || zf >= nz)) {
+                            const double *u_w = zf < 0 ? uw : uw + 3;
+                            F[i * n + s] = Fp[opp(i) * n + s] +
+                                           6.0 * W[i] * rp[s] * (E[i][0] * u_w[0] + E[i][1] * u_w[1] + E[i][2] * u_w[2]);
+                        } else {
+                            F[i * n + s] = Fp[i * n + site(nx, ny, wrap(x - E[i][0], nx), wrap(y - E[i][1], ny), wrap(zf, nz))];
+                        }
                     }
                 }
-        for (long k = 0; k < Q * n; k++) F[k] = Fp[k];
     }
     free(Fp);
+    free(rp);
     return 0;
 }
 
-/* Moments of the standard model: rho = sum f, u = sum f e / rho. */
-void orc_moments_std(int nx, int ny, int nz, const double *F, double *rho, double *u)
+int orc_step_std(int nx, int ny, int nz, double tau, const double *Tf, double *F, long nsteps)
+{
+    return orc_step_std_walls(nx, ny, nz, tau, Tf, NULL, NULL, F, nsteps);
+}
+
+/* Moments of the standard model: rho = sum f, u = (sum f e + rho a / 2) / rho (accel or NULL). */
+void orc_moments_std_ext(int nx, int ny, int nz, const double *accel, const double *F, double *rho, double *u)
 {
     const long n = (long)nx * ny * nz;
     for (long s = 0; s < n; s++) {
-        double r = 0.0, j[3] = {0.0, 0.0, 0.0};
-        for (int i = 0; i < Q; i++) {
-            r += F[i * n + s];
-            for (int a = 0; a < 3; a++) j[a] += F[i * n + s] * E[i][a];
-        }
-        rho[s] = r;
-        for (int a = 0; a < 3; a++) u[a * n + s] = j[a] / r;
+        double Fs[Q], a[3], uu[3];
+        for (int i = 0; i < Q; i++) Fs[i] = F[i * n + s];
+        if (accel)
+            for (int c = 0; c < 3; c++) a[c] = accel[c * n + s];
+        std_velocity(Fs, accel ? a : NULL, rho + s, uu);
+        for (int c = 0; c < 3; c++) u[c * n + s] = uu[c];
     }
+}
+
+void orc_moments_std(int nx, int ny, int nz, const double *F, double *rho, double *u)
+{
+    orc_moments_std_ext(nx, ny, nz, NULL, F, rho, u);
 }

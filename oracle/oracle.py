@@ -54,6 +54,13 @@ def _load():
         _lib.orc_step_std.argtypes = [i, i, i, d, P, P, l]
         _lib.orc_step_std.restype = i
         _lib.orc_moments_std.argtypes = [i, i, i, P, P, P]
+        _lib.orc_step_walls.argtypes = [i, i, i, d, d, i, P, P, P, P, P, l]
+        _lib.orc_step_walls.restype = i
+        _lib.orc_moments_walls.argtypes = [i, i, i, d, i, P, P, i, P, P, P, P, P]
+        _lib.orc_moments_walls.restype = i
+        _lib.orc_step_std_walls.argtypes = [i, i, i, d, P, P, P, P, l]
+        _lib.orc_step_std_walls.restype = i
+        _lib.orc_moments_std_ext.argtypes = [i, i, i, P, P, P, P]
     return _lib
 
 
@@ -122,7 +129,8 @@ MODES = {"thermal": 0, "iso": 1, "standard": 2}
 
 
 class OracleLattice:
-    """A periodic nx*ny*nz lattice stepped by the oracle, state held in numpy arrays."""
+    """An nx*ny*nz lattice stepped by the oracle, state held in numpy arrays. Periodic in x and y;
+    in z periodic, or bounded by two moving walls (set_walls)."""
 
     def __init__(self, nx, ny, nz, tau, mode="thermal", T_field=None, tau_ghost=None):
         """tau_ghost: relaxation time of the non-hydrodynamic moments (rows 11-19 of Table I);
@@ -132,6 +140,7 @@ class OracleLattice:
         self.tau = float(tau)
         self.tau_ghost = self.tau if tau_ghost is None else float(tau_ghost)
         self.accel = None  # body-force acceleration field (3, nz, ny, nx), or None
+        self.walls = None  # (u_bottom, u_top) as 6 float64 values, or None (periodic in z)
         self.mode = MODES[mode]
         shape = (self.nz, self.ny, self.nx)
         self.F = np.zeros((19,) + shape)
@@ -166,6 +175,17 @@ class OracleLattice:
             self.accel = _f64(np.broadcast_to(np.asarray(accel, dtype=np.float64).reshape(
                 (3,) + (1,) * 3 if np.size(accel) == 3 else (3,) + self.shape), (3,) + self.shape))
 
+    def set_walls(self, u_bottom=None, u_top=None, on=True):
+        """Walls normal to z half-way outside the first and last planes (half-way bounce-back),
+        moving with the tangential velocities u_bottom and u_top (3-vectors, default at rest).
+        on=False restores the periodic z direction."""
+        if not on:
+            self.walls = None
+            return
+        ub = np.zeros(3) if u_bottom is None else np.asarray(u_bottom, dtype=np.float64).reshape(3)
+        ut = np.zeros(3) if u_top is None else np.asarray(u_top, dtype=np.float64).reshape(3)
+        self.walls = _f64(np.concatenate([ub, ut]))
+
     def set_state(self, F, b):
         self.F = _f64(F).reshape((19,) + self.shape).copy()
         self.b = _f64(b).reshape((6,) + self.shape).copy()
@@ -174,12 +194,16 @@ class OracleLattice:
         return self.F.copy(), self.b.copy()
 
     def step(self, n=1):
+        acc = None if self.accel is None else _p(self.accel)
+        uw = None if self.walls is None else _p(self.walls)
         if self.mode == 2:
-            rc = _load().orc_step_std(self.nx, self.ny, self.nz, self.tau, _p(self.T_field), _p(self.F), int(n))
+            rc = _load().orc_step_std_walls(self.nx, self.ny, self.nz, self.tau, _p(self.T_field), acc, uw,
+                                            _p(self.F), int(n))
         else:
-            acc = None if self.accel is None else _p(self.accel)
-            rc = _load().orc_step_ext(self.nx, self.ny, self.nz, self.tau, self.tau_ghost, self.mode,
-                                      _p(self.T_field), acc, _p(self.F), _p(self.b), int(n))
+            rc = _load().orc_step_walls(self.nx, self.ny, self.nz, self.tau, self.tau_ghost, self.mode,
+                                        _p(self.T_field), acc, uw, _p(self.F), _p(self.b), int(n))
+        if rc == -3:
+            raise ValueError("walls need nz >= 3 and tangential wall velocities")
         if rc != 0:
             raise MemoryError("oracle step failed")
         self.steps += int(n)
@@ -188,12 +212,12 @@ class OracleLattice:
         rho = np.zeros(self.shape)
         u = np.zeros((3,) + self.shape)
         T = np.zeros(self.shape)
-        if self.mode == 2:
-            _load().orc_moments_std(self.nx, self.ny, self.nz, _p(self.F), _p(rho), _p(u))
-            return rho, u, self.T_field.copy()
         acc = None if self.accel is None else _p(self.accel)
-        rc = _load().orc_moments_ext(self.nx, self.ny, self.nz, self.tau, self.mode, _p(self.T_field), acc,
-                                     _p(self.F), _p(self.b), _p(rho), _p(u), _p(T))
+        if self.mode == 2:
+            _load().orc_moments_std_ext(self.nx, self.ny, self.nz, acc, _p(self.F), _p(rho), _p(u))
+            return rho, u, self.T_field.copy()
+        rc = _load().orc_moments_walls(self.nx, self.ny, self.nz, self.tau, self.mode, _p(self.T_field), acc,
+                                       int(self.walls is not None), _p(self.F), _p(self.b), _p(rho), _p(u), _p(T))
         if rc != 0:
             raise MemoryError("oracle moments failed")
         return rho, u, T
