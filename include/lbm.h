@@ -146,11 +146,22 @@ int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost);
 /* Body-force acceleration field: 3n values of `dtype` (x, y, z planes, x fastest), or NULL to
  * remove it.  It enters the forcing moments of Eqs. 58-61 as F += rho a and S += rho (u a + a u)
  * with the corrected velocity of Eq. 57, which then carries half of rho a (a Guo-type forcing;
- * the paper drives its Poiseuille and Couette flows with a body force, Sec. III A and C).  The
+ * the paper drives its Poiseuille and Couette flows with a body force, Sec. III A and C).  In
+ * the STANDARD mode the same F and S build the forcing, with u = (j + rho a / 2) / rho.  The
  * field is copied (3 planes of the compute type on the device).  A lattice with a body force
- * steps with the two-pass kernel.  Errors: ARG (dtype, STANDARD mode, fused kernel forced), OOM,
- * HIP. */
+ * steps with the two-pass kernel.  Errors: ARG (dtype, fused kernel forced), OOM, HIP. */
 int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device);
+
+/* Walls normal to z (the channels of Sec. III A and C): on = 1 places one wall half-way below
+ * plane 0 and one half-way above plane nz - 1 (z = -1/2 and nz - 1/2); x and y stay periodic.
+ * u_bottom, u_top: host arrays of 3 wall velocities (NULL: at rest); the z components must be 0.
+ * A population that would stream through a wall returns reversed to its site (half-way
+ * bounce-back) carrying the moving-wall momentum of Ladd, 6 w_i rho e_i.u_w, and the site's own
+ * variance.  Beyond a wall the gradient sources of Eqs. 59 and 61 take the wall-adjacent
+ * plane's rho b (mirrored) and the second-order extrapolation of rho b u*.  on = 0 restores the
+ * periodic z direction.  Applies to every mode; a lattice with walls steps with the two-pass
+ * kernel.  Errors: ARG (nz < 3, a normal or non-finite wall velocity, the fused kernel forced). */
+int lbm_set_walls(lbm_handle h, int on, const double *u_bottom, const double *u_top);
 
 /* Block until all work queued on the lattice's stream is done. */
 int lbm_sync(lbm_handle h);

@@ -59,7 +59,7 @@ size_t compute_bytes(int storage) { return storage == LBM_F64 ? 8 : 4; }
 
 namespace {
 
-Geo geo(const lbm_lattice *h) { return Geo{h->p.nx, h->p.ny, h->p.nz, h->n}; }
+Geo geo(const lbm_lattice *h) { return Geo{h->p.nx, h->p.ny, h->p.nz, h->n, h->walls}; }
 
 int blocks_for(int n) { return (n + BLOCK - 1) / BLOCK; }
 int red_blocks(int n) {
@@ -78,6 +78,10 @@ template <typename C> StepConst<C> step_const(const lbm_lattice *h) {
     k.K = (C)(h->p.rho_ref * (h->p.T_ref - 1.0 / 3.0));
     k.om1 = (C)(1.0 - omega);
     k.ghost = h->tau_ghost > 0.0 ? (C)(1.0 - (1.0 / (h->tau_ghost + 0.5)) / omega) : C(0);
+    for (int c = 0; c < 3; c++) {
+        k.uwb[c] = (C)h->uw[c];
+        k.uwt[c] = (C)h->uw[3 + c];
+    }
     k.iso = h->p.mode == LBM_ISO;
     return k;
 }
@@ -177,23 +181,19 @@ template <int S> int step_two_pass(lbm_lattice *h) {
     const C *Tf = (const C *)h->Tf;
     const C Tc = (C)h->Tconst;
     const dim3 grid(blocks_for(h->n)), block(BLOCK);
-    if (h->gathered) {
-        hipLaunchKernelGGL((k_predict<S, true>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k, h->codec);
-        if (h->tau_ghost > 0.0)
-            hipLaunchKernelGGL((k_collide<S, true, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag,
-                               (const C *)h->accel);
-        else
-            hipLaunchKernelGGL((k_collide<S, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag,
-                               (const C *)h->accel);
-    } else {
-        hipLaunchKernelGGL((k_predict<S, false>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k, h->codec);
-        if (h->tau_ghost > 0.0)
-            hipLaunchKernelGGL((k_collide<S, false, true>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag,
-                               (const C *)h->accel);
-        else
-            hipLaunchKernelGGL((k_collide<S, false>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k, h->codec, h->flag,
-                               (const C *)h->accel);
-    }
+    auto launch = [&](auto GI, auto MI, auto WI) {
+        constexpr bool G = decltype(GI)::value, M = decltype(MI)::value, W = decltype(WI)::value;
+        hipLaunchKernelGGL((k_predict<S, G>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k, h->codec);
+        hipLaunchKernelGGL((k_collide<S, G, M, W>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k,
+                           h->codec, h->flag, (const C *)h->accel);
+    };
+    auto with_walls = [&](auto GI, auto MI) {
+        if (h->walls) launch(GI, MI, std::true_type{}); else launch(GI, MI, std::false_type{});
+    };
+    auto with_mrt = [&](auto GI) {
+        if (h->tau_ghost > 0.0) with_walls(GI, std::true_type{}); else with_walls(GI, std::false_type{});
+    };
+    if (h->gathered) with_mrt(std::true_type{}); else with_mrt(std::false_type{});
     int rc = check_launch();
     if (rc) return rc;
     h->cur = 1 - h->cur;
@@ -221,9 +221,12 @@ template <int S> int step_fused(lbm_lattice *h) {
 template <int S> int step_std(lbm_lattice *h) {
     using T = typename Storage<S>::T;
     using C = typename Storage<S>::C;
-    hipLaunchKernelGGL((k_std<S>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream, (const T *)h->F[h->cur],
-                       (T *)h->F[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, geo(h), step_const<C>(h), h->codec,
-                       h->flag);
+    auto launch = [&](auto WI) {
+        hipLaunchKernelGGL((k_std<S, decltype(WI)::value>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream,
+                           (const T *)h->F[h->cur], (T *)h->F[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, geo(h),
+                           step_const<C>(h), h->codec, h->flag, (const C *)h->accel);
+    };
+    if (h->walls) launch(std::true_type{}); else launch(std::false_type{});
     int rc = check_launch();
     if (rc) return rc;
     // bbar carries nothing in this model: both buffers hold its reference (zero deviation) since
@@ -235,7 +238,7 @@ template <int S> int step_std(lbm_lattice *h) {
 
 // the fused sweep relaxes with a single rate; a lattice with its own ghost rate steps two-pass
 bool use_fused(const lbm_lattice *h) {
-    return h->kernel != 1 && h->tau_ghost <= 0.0 && !h->accel && fused_supported(geo(h), h->p.storage);
+    return h->kernel != 1 && h->tau_ghost <= 0.0 && !h->accel && !h->walls && fused_supported(geo(h), h->p.storage);
 }
 
 }  // namespace
@@ -324,7 +327,31 @@ int lbm_set_kernel(lbm_handle h, int kernel) {
     if (kernel == 2 && h->tau_ghost > 0.0)
         return fail(LBM_ERR_ARG, "the fused sweep relaxes with a single rate (a ghost rate is set)");
     if (kernel == 2 && h->accel) return fail(LBM_ERR_ARG, "the fused sweep has no body force (one is set)");
+    if (kernel == 2 && h->walls) return fail(LBM_ERR_ARG, "the fused sweep is periodic (walls are set)");
     h->kernel = kernel;
+    return LBM_OK;
+}
+
+int lbm_set_walls(lbm_handle h, int on, const double *u_bottom, const double *u_top) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (!on) {
+        h->walls = 0;
+        for (int c = 0; c < 6; c++) h->uw[c] = 0.0;
+        return LBM_OK;
+    }
+    if (h->p.nz < 3) return fail(LBM_ERR_ARG, "walls need nz >= 3 (got %d)", h->p.nz);
+    if (h->kernel == 2) return fail(LBM_ERR_ARG, "the fused sweep is periodic (lbm_set_kernel chose it)");
+    double uw[6] = {0, 0, 0, 0, 0, 0};
+    for (int c = 0; c < 3; c++) {
+        if (u_bottom) uw[c] = u_bottom[c];
+        if (u_top) uw[3 + c] = u_top[c];
+    }
+    for (int c = 0; c < 6; c++)
+        if (!std::isfinite(uw[c])) return fail(LBM_ERR_ARG, "wall velocity not finite");
+    if (uw[2] != 0.0 || uw[5] != 0.0) return fail(LBM_ERR_ARG, "a wall cannot move along its normal (z)");
+    // the step after a change reads the new walls; bbar already gathered stays valid
+    h->walls = 1;
+    for (int c = 0; c < 6; c++) h->uw[c] = uw[c];
     return LBM_OK;
 }
 
@@ -337,7 +364,6 @@ int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device
     }
     if (!accel) return LBM_OK;
     if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_ARG, "unknown dtype %d", dtype);
-    if (h->p.mode == LBM_STANDARD) return fail(LBM_ERR_ARG, "the standard comparator has no body force");
     if (h->kernel == 2) return fail(LBM_ERR_ARG, "the fused sweep has no body force (lbm_set_kernel chose it)");
     const size_t count = 3 * (size_t)h->n, eb = dtype == LBM_DTYPE_F64 ? 8 : 4;
     HIP_TRY(hipMalloc(&h->accel, compute_bytes(h->p.storage) * count));
@@ -549,7 +575,8 @@ int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on
             using OUT = typename decltype(OI)::type;
             if (h->p.mode == LBM_STANDARD) {
                 hipLaunchKernelGGL((k_readout_std<S, OUT>), grid, block, 0, h->stream, F, (const C *)h->Tf,
-                                   (C)h->Tconst, g, k, h->codec, h->p.T_ref, (OUT *)dr, (OUT *)du, (OUT *)dT);
+                                   (C)h->Tconst, g, k, h->codec, h->p.T_ref, (OUT *)dr, (OUT *)du, (OUT *)dT,
+                                   (const C *)h->accel);
                 return;
             }
             hipLaunchKernelGGL((k_predict<S, G>), grid, block, 0, h->stream, F, B, src, (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);

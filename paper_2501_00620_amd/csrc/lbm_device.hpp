@@ -34,6 +34,8 @@ constexpr int NFIELD = Q + NB;
 constexpr int EX[Q] = {0, 1, 0, -1, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0};
 constexpr int EY[Q] = {0, 0, 1, 0, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1};
 constexpr int EZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+// Index of -e_i (half-way bounce-back).
+constexpr int OPP[Q] = {0, 3, 4, 1, 2, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
 // Weights w_i = feq_i(u = 0) / rho (Appendix A at rest): 1/3, 1/18 (faces), 1/36 (edges).
 constexpr double WQ[Q] = {1.0 / 3, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
@@ -143,6 +145,8 @@ template <typename C> struct StepConst {
     C K;          // rho_ref * theta_ref
     C om1;        // 1 - omega
     C ghost;      // 1 - omega_g / omega: the non-hydrodynamic moments' own rate (0: single rate)
+    C uwb[3];     // velocity of the wall below plane 0 (walls; tangential)
+    C uwt[3];     // velocity of the wall above plane nz - 1
     int iso;      // prescribed temperature (theta per site or constant)
 };
 
@@ -280,6 +284,44 @@ __device__ __forceinline__ void grad_add(GradAcc<C> &g, const C s[NSRC], C K) {
     S[3] = fma(wx, uy, fma(wy, ux, S[3]));
     S[4] = fma(wx, uz, fma(wz, ux, S[4]));
     S[5] = fma(wy, uz, fma(wz, uy, S[5]));
+}
+
+// The same term for a neighbour one plane beyond a wall, from the three planes of its column
+// inside the wall, s0 (the wall-adjacent plane), s1, s2: the variance pressure R is mirrored
+// (R(s0)), the products R u* are extrapolated to second order, 3 X(s0) - 3 X(s1) + X(s2).
+template <typename C, int I, bool HASK = true>
+__device__ __forceinline__ void grad_add_wall(GradAcc<C> &g, const C s0[NSRC], const C s1[NSRC], const C s2[NSRC],
+                                              C K) {
+    constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
+    constexpr bool face = (ex * ex + ey * ey + ez * ez) == 1;
+    C *F = face ? g.fF : g.eF;
+    C *S = face ? g.fS : g.eS;
+    F[0] += C(ex) * s0[0] + C(ey) * s0[3] + C(ez) * s0[4];
+    F[1] += C(ex) * s0[3] + C(ey) * s0[1] + C(ez) * s0[5];
+    F[2] += C(ex) * s0[4] + C(ey) * s0[5] + C(ez) * s0[2];
+    auto add = [&](const C *s, C c) {
+        C wx = C(ex) * s[0] + C(ey) * s[3] + C(ez) * s[4];
+        C wy = C(ex) * s[3] + C(ey) * s[1] + C(ez) * s[5];
+        C wz = C(ex) * s[4] + C(ey) * s[5] + C(ez) * s[2];
+        if constexpr (HASK) {
+            wx += C(ex) * K;
+            wy += C(ey) * K;
+            wz += C(ez) * K;
+        }
+        wx *= c;
+        wy *= c;
+        wz *= c;
+        const C ux = s[6], uy = s[7], uz = s[8];
+        S[0] = fma(wx, ux, S[0]);
+        S[1] = fma(wy, uy, S[1]);
+        S[2] = fma(wz, uz, S[2]);
+        S[3] = fma(wx, uy, fma(wy, ux, S[3]));
+        S[4] = fma(wx, uz, fma(wz, ux, S[4]));
+        S[5] = fma(wy, uz, fma(wz, uy, S[5]));
+    };
+    add(s0, C(3));
+    add(s1, C(-3));
+    add(s2, C(1));
 }
 
 template <typename C>
@@ -526,6 +568,20 @@ __device__ __forceinline__ void equilibrium_std_dev(C drho, C rho, C ux, C uy, C
         const C eu = C(ex) * ux + C(ey) * uy + C(ez) * uz;
         const C br = fma(eu, fma(C(4.5), eu, C(3)), fma(C(4.5 * e2), th, a));
         f[I] = C(WQ[I]) * fma(rho, br, drho);
+    });
+}
+
+// Forcing populations from their moments F and S (Eqs. 58-61 with no ghost moments), in Hermite
+// form: Phi_i = w_i [3 e_i.F + 9/2 (e_i e_i - I/3) : S].  S is ordered xx yy zz xy xz yz.
+template <typename C>
+__device__ __forceinline__ void forcing_pops(const C F[3], const C S[6], C phi[Q]) {
+    const C t3 = (S[0] + S[1] + S[2]) * C(1.0 / 3.0);
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
+        const C eF = C(ex) * F[0] + C(ey) * F[1] + C(ez) * F[2];
+        const C eSe = C(ex * ex) * S[0] + C(ey * ey) * S[1] + C(ez * ez) * S[2] +
+                      C(2 * ex * ey) * S[3] + C(2 * ex * ez) * S[4] + C(2 * ey * ez) * S[5];
+        phi[I] = C(WQ[I]) * fma(C(3), eF, C(4.5) * (eSe - t3));
     });
 }
 

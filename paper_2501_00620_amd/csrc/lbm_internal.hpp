@@ -28,6 +28,8 @@ struct lbm_lattice {
     int slots = 256;            // fused work-groups resident at once (one per CU)
     double tau_ghost = -1.0;    // relaxation time of Table I rows 11-19 (<= 0: the single rate)
     void *accel = nullptr;      // body-force acceleration, 3 planes of the compute type, or null
+    int walls = 0;              // 1: walls normal to z bound the lattice (lbm_set_walls)
+    double uw[6] = {0, 0, 0, 0, 0, 0};  // velocities of the bottom and top walls
 };
 
 namespace lbm {

@@ -13,6 +13,13 @@
 //   src   : 9 planes of n compute-type values, the predictor sources rho*b (6) and u* (3).
 // The step pushes fbar*_i(x) to x + e_i and stores bbar*(x) at x, so the populations are always
 // held post-stream and bbar becomes scattered after the first step.
+//
+// Walls (Geo::walls): two planes normal to z, half-way outside planes 0 and nz - 1 (the channels
+// of Sec. III A and C); x and y stay periodic.  A population pushed through a wall lands in the
+// opposite slot of its own site (half-way bounce-back) with the moving-wall momentum
+// -6 w_i rho e_i.u_w; its gather weight takes the site's own bbar* (a reversal maps the second
+// moment onto itself).  Beyond a wall the gradient sources are the wall-adjacent plane's rho b
+// (mirrored) and the second-order extrapolation of rho b u* (grad_add_wall).
 #pragma once
 
 #include <type_traits>
@@ -25,8 +32,23 @@ constexpr int BLOCK = 256;
 
 struct Geo {
     int nx, ny, nz;
-    int n;  // sites
+    int n;          // sites
+    int walls = 0;  // 1: walls bound z (see the header), 0: periodic
 };
+
+// Bit 0: the site is next to the wall below plane 0; bit 1: next to the wall above plane nz - 1.
+__device__ __forceinline__ int wall_bits(const Geo &g, int z) {
+    return g.walls ? (int)(z == 0) | ((int)(z == g.nz - 1) << 1) : 0;
+}
+
+// Population I arriving at a site with wall bits zw came back through a wall (x - e_I is beyond).
+template <int I> __device__ __forceinline__ bool arrives_from_wall(int zw) {
+    return (EZ[I] == 1 && (zw & 1)) || (EZ[I] == -1 && (zw & 2));
+}
+// Population I leaving a site with wall bits zw goes into a wall (x + e_I is beyond).
+template <int I> __device__ __forceinline__ bool leaves_into_wall(int zw) {
+    return (EZ[I] == -1 && (zw & 1)) || (EZ[I] == 1 && (zw & 2));
+}
 
 __device__ __forceinline__ void site_xyz(int s, const Geo &g, int &x, int &y, int &z) {
     x = s % g.nx;
@@ -43,7 +65,7 @@ __device__ __forceinline__ void load_site(const typename Storage<S>::T *__restri
                                           const typename Storage<S>::T *__restrict__ B, size_t n,
                                           const Nbr &nb, int s, const Codec &cd, typename Storage<S>::C rho_ref,
                                           typename Storage<S>::C f[Q], typename Storage<S>::C bbar[NB],
-                                          PopMoments<typename Storage<S>::C> &m) {
+                                          PopMoments<typename Storage<S>::C> &m, int zw = 0) {
     using C = typename Storage<S>::C;
     Unroll<0, Q>::run([&](auto I) { f[I] = Storage<S>::load(F, (size_t)I * n + s, I, cd); });
     m = pop_moments(f, rho_ref);
@@ -55,7 +77,7 @@ __device__ __forceinline__ void load_site(const typename Storage<S>::T *__restri
 #pragma unroll
         for (int c = 0; c < NB; c++) acc[c] = C(0);
         Unroll<0, Q>::run([&](auto I) {
-            const int up = nb.at(-EX[I], -EY[I], -EZ[I]);
+            const int up = arrives_from_wall<I>(zw) ? s : nb.at(-EX[I], -EY[I], -EZ[I]);
             const C wgt = fma(C(WQ[I]), rho_ref, f[I]);
 #pragma unroll
             for (int c = 0; c < NB; c++) acc[c] += wgt * Storage<S>::load(B, (size_t)c * n + up, Q + c, cd);
@@ -85,20 +107,35 @@ k_predict(const typename Storage<S>::T *__restrict__ F, const typename Storage<S
     const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
     C f[Q], bbar[NB];
     PopMoments<C> m;
-    load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, f, bbar, m);
+    load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, f, bbar, m, wall_bits(g, z));
     C o[NSRC];
     predictor_sources(m, bbar, site_T(Tf, Tconst, s), k, o);
 #pragma unroll
     for (int c = 0; c < NSRC; c++) src[(size_t)c * g.n + s] = o[c];
 }
 
-// Gradient forcing moments at a site from the source planes.
-template <typename C>
+// Gradient forcing moments at a site from the source planes.  WALLS: the lattice has walls;
+// zw: wall bits of the site; nxy: the plane stride (used only next to a wall).
+template <bool WALLS, typename C>
 __device__ __forceinline__ void gradient_from_src(const C *__restrict__ src, size_t n, const Nbr &nb, C K,
-                                                  C F[3], C S[6]) {
+                                                  C F[3], C S[6], int zw = 0, int nxy = 0) {
     GradAcc<C> acc;
     grad_init(acc);
     Unroll<1, Q>::run([&](auto I) {
+        if (WALLS && leaves_into_wall<I>(zw)) {
+            // the column of the neighbour, inwards from the wall-adjacent plane
+            const int base = nb.at(EX[I], EY[I], 0);
+            const int step = EZ[I] < 0 ? nxy : -nxy;
+            C s0[NSRC], s1[NSRC], s2[NSRC];
+#pragma unroll
+            for (int c = 0; c < NSRC; c++) {
+                s0[c] = src[(size_t)c * n + base];
+                s1[c] = src[(size_t)c * n + base + step];
+                s2[c] = src[(size_t)c * n + base + 2 * step];
+            }
+            grad_add_wall<C, I>(acc, s0, s1, s2, K);
+            return;
+        }
         const int at = nb.at(EX[I], EY[I], EZ[I]);
         C sv[NSRC];
 #pragma unroll
@@ -109,8 +146,9 @@ __device__ __forceinline__ void gradient_from_src(const C *__restrict__ src, siz
 }
 
 // ---- pass B: gradients, collision, push-stream ------------------------------------------------
-// MRT: the non-hydrodynamic moments relax at their own rate (ghost_relax).
-template <int S, bool GATHERED, bool MRT = false>
+// MRT: the non-hydrodynamic moments relax at their own rate (ghost_relax).  WALLS: the lattice
+// has walls (the periodic instantiation carries no wall code).
+template <int S, bool GATHERED, bool MRT = false, bool WALLS = false>
 __global__ void __launch_bounds__(BLOCK)
 k_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
           const typename Storage<S>::C *__restrict__ src, typename Storage<S>::T *__restrict__ Fo,
@@ -123,11 +161,12 @@ k_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S
     int x, y, z;
     site_xyz(s, g, x, y, z);
     const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    const int zw = WALLS ? wall_bits(g, z) : 0;
     C f[Q], bbar[NB];
     PopMoments<C> m;
-    load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, f, bbar, m);
+    load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, f, bbar, m, zw);
     C Fv[3], Sv[6];
-    gradient_from_src(src, g.n, nb, k.K, Fv, Sv);
+    gradient_from_src<WALLS>(src, g.n, nb, k.K, Fv, Sv, zw, g.nx * g.ny);
     if (accel) {  // body force (uniform branch: one field for the whole lattice)
         const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
         add_body_force(m, a, Fv, Sv);
@@ -141,7 +180,13 @@ k_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S
     if constexpr (MRT) ghost_relax(f0, f, k.ghost);
     unsigned sat = 0;
     Unroll<0, Q>::run([&](auto I) {
-        Storage<S>::store(Fo, (size_t)I * g.n + nb.at(EX[I], EY[I], EZ[I]), I, f[I], cd, sat);
+        if (WALLS && leaves_into_wall<I>(zw)) {  // half-way bounce-back, moving-wall momentum
+            const C *uw = EZ[I] < 0 ? k.uwb : k.uwt;
+            const C mom = C(6.0 * WQ[I]) * m.rho * (C(EX[I]) * uw[0] + C(EY[I]) * uw[1]);
+            Storage<S>::store(Fo, (size_t)OPP[I] * g.n + s, OPP[I], f[I] - mom, cd, sat);
+        } else {
+            Storage<S>::store(Fo, (size_t)I * g.n + nb.at(EX[I], EY[I], EZ[I]), I, f[I], cd, sat);
+        }
     });
 #pragma unroll
     for (int c = 0; c < NB; c++) Storage<S>::store(Bo, (size_t)c * g.n + s, Q + c, bbar[c], cd, sat);
@@ -162,11 +207,12 @@ k_readout(const typename Storage<S>::T *__restrict__ F, const typename Storage<S
     int x, y, z;
     site_xyz(s, g, x, y, z);
     const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    const int zw = wall_bits(g, z);
     C f[Q], bbar[NB];
     PopMoments<C> m;
-    load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, f, bbar, m);
+    load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, f, bbar, m, zw);
     C Fv[3], Sv[6];
-    gradient_from_src(src, g.n, nb, k.K, Fv, Sv);
+    gradient_from_src<true>(src, g.n, nb, k.K, Fv, Sv, zw, g.nx * g.ny);
     if (accel) {
         const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
         add_body_force(m, a, Fv, Sv);
@@ -237,48 +283,82 @@ k_init_std(const IN *__restrict__ rho, const IN *__restrict__ u, const IN *__res
 }
 
 // One step: BGK with the scheme's relaxation factor, d' = (1 - omega) d + omega d_eq, and the
-// push to the 19 neighbours.
-template <int S>
+// push to the 19 neighbours.  With a body force a: u = (j + rho a / 2) / rho and the forcing
+// (1 - omega/2) Phi of F = rho a, S = rho (u a + a u); no gradient forcing (no variance).
+// Walls as in the bump scheme (the header).
+template <int S, bool WALLS = false>
 __global__ void __launch_bounds__(BLOCK)
 k_std(const typename Storage<S>::T *__restrict__ F, typename Storage<S>::T *__restrict__ Fo,
       const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
-      StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag) {
+      StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag,
+      const typename Storage<S>::C *__restrict__ accel) {
     using C = typename Storage<S>::C;
     const int s = blockIdx.x * BLOCK + threadIdx.x;
     if (s >= g.n) return;
     int x, y, z;
     site_xyz(s, g, x, y, z);
     const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    const int zw = WALLS ? wall_bits(g, z) : 0;
     C d[Q], feq[Q];
     Unroll<0, Q>::run([&](auto I) { d[I] = Storage<S>::load(F, (size_t)I * g.n + s, I, cd); });
     const PopMoments<C> m = pop_moments(d, k.rho_ref);
     const C inv = recip(m.rho);
-    equilibrium_std_dev(m.drho, m.rho, m.jx * inv, m.jy * inv, m.jz * inv, site_T(Tf, Tconst, s) + k.theta_ref, feq);
+    const C th = site_T(Tf, Tconst, s) + k.theta_ref;
+    if (accel) {  // uniform branch: one field for the whole lattice
+        const C Fv[3] = {m.rho * accel[s], m.rho * accel[(size_t)g.n + s], m.rho * accel[2 * (size_t)g.n + s]};
+        const C u[3] = {fma(C(0.5), Fv[0], m.jx) * inv, fma(C(0.5), Fv[1], m.jy) * inv,
+                        fma(C(0.5), Fv[2], m.jz) * inv};
+        const C Sv[6] = {C(2) * u[0] * Fv[0], C(2) * u[1] * Fv[1], C(2) * u[2] * Fv[2],
+                         fma(u[0], Fv[1], u[1] * Fv[0]), fma(u[0], Fv[2], u[2] * Fv[0]),
+                         fma(u[1], Fv[2], u[2] * Fv[1])};
+        C phi[Q];
+        forcing_pops(Fv, Sv, phi);
+        equilibrium_std_dev(m.drho, m.rho, u[0], u[1], u[2], th, feq);
+#pragma unroll
+        for (int i = 0; i < Q; i++) feq[i] = fma(k.fcoef, phi[i], k.omega * feq[i]);
+    } else {
+        equilibrium_std_dev(m.drho, m.rho, m.jx * inv, m.jy * inv, m.jz * inv, th, feq);
+#pragma unroll
+        for (int i = 0; i < Q; i++) feq[i] = k.omega * feq[i];
+    }
     unsigned sat = 0;
     Unroll<0, Q>::run([&](auto I) {
-        Storage<S>::store(Fo, (size_t)I * g.n + nb.at(EX[I], EY[I], EZ[I]), I, fma(k.om1, d[I], k.omega * feq[I]), cd,
-                          sat);
+        const C post = fma(k.om1, d[I], feq[I]);
+        if (WALLS && leaves_into_wall<I>(zw)) {
+            const C *uw = EZ[I] < 0 ? k.uwb : k.uwt;
+            const C mom = C(6.0 * WQ[I]) * m.rho * (C(EX[I]) * uw[0] + C(EY[I]) * uw[1]);
+            Storage<S>::store(Fo, (size_t)OPP[I] * g.n + s, OPP[I], post - mom, cd, sat);
+        } else {
+            Storage<S>::store(Fo, (size_t)I * g.n + nb.at(EX[I], EY[I], EZ[I]), I, post, cd, sat);
+        }
     });
     if (sat) *flag = 1u;
 }
 
-// Moments of the standard model: rho, u = j / rho, and the prescribed T.
+// Moments of the standard model: rho, u = (j + rho a / 2) / rho (a: the body force, or none),
+// and the prescribed T.
 template <int S, typename OUT>
 __global__ void __launch_bounds__(BLOCK)
 k_readout_std(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::C *__restrict__ Tf,
               typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd, double T_ref,
-              OUT *__restrict__ rho, OUT *__restrict__ u, OUT *__restrict__ T) {
+              OUT *__restrict__ rho, OUT *__restrict__ u, OUT *__restrict__ T,
+              const typename Storage<S>::C *__restrict__ accel) {
     using C = typename Storage<S>::C;
     const int s = blockIdx.x * BLOCK + threadIdx.x;
     if (s >= g.n) return;
     C d[Q];
     Unroll<0, Q>::run([&](auto I) { d[I] = Storage<S>::load(F, (size_t)I * g.n + s, I, cd); });
     const PopMoments<C> m = pop_moments(d, k.rho_ref);
+    C j[3] = {m.jx, m.jy, m.jz};
+    if (accel) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) j[c] = fma(C(0.5) * m.rho, accel[(size_t)c * g.n + s], j[c]);
+    }
     if (rho) rho[s] = (OUT)((double)k.rho_ref + (double)m.drho);
     if (u) {
-        u[s] = (OUT)(m.jx / m.rho);
-        u[(size_t)g.n + s] = (OUT)(m.jy / m.rho);
-        u[2 * (size_t)g.n + s] = (OUT)(m.jz / m.rho);
+        u[s] = (OUT)(j[0] / m.rho);
+        u[(size_t)g.n + s] = (OUT)(j[1] / m.rho);
+        u[2 * (size_t)g.n + s] = (OUT)(j[2] / m.rho);
     }
     if (T) T[s] = (OUT)(T_ref + (double)site_T(Tf, Tconst, s));
 }
@@ -314,7 +394,7 @@ k_decode_state(const typename Storage<S>::T *__restrict__ F, const typename Stor
     const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
     C f[Q], bbar[NB];
     PopMoments<C> m;
-    load_site<S, GATHERED>(F, B, g.n, nb, s, cd, rho_ref, f, bbar, m);
+    load_site<S, GATHERED>(F, B, g.n, nb, s, cd, rho_ref, f, bbar, m, wall_bits(g, z));
     if (Fout) {
 #pragma unroll
         for (int i = 0; i < Q; i++) Fout[(size_t)i * g.n + s] = cd.ref[i] + (double)f[i];
@@ -406,7 +486,7 @@ k_invariants(const typename Storage<S>::T *__restrict__ F, const typename Storag
         const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
         C f[Q], bbar[NB];
         PopMoments<C> m;
-        load_site<S, GATHERED>(F, B, g.n, nb, s, cd, rho_ref, f, bbar, m);
+        load_site<S, GATHERED>(F, B, g.n, nb, s, cd, rho_ref, f, bbar, m, wall_bits(g, z));
         const double rho = (double)rho_ref + (double)m.drho;
         v[0] += rho;
         v[1] += (double)m.jx;
@@ -433,7 +513,7 @@ k_health(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>
         const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
         C f[Q], bbar[NB];
         PopMoments<C> m;
-        load_site<S, GATHERED>(F, B, g.n, nb, s, cd, rho_ref, f, bbar, m);
+        load_site<S, GATHERED>(F, B, g.n, nb, s, cd, rho_ref, f, bbar, m, wall_bits(g, z));
         bool finite = true;
 #pragma unroll
         for (int i = 0; i < Q; i++) finite = finite && isfinite((double)f[i]);

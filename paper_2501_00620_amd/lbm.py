@@ -52,6 +52,7 @@ SIGNATURES = {
     "lbm_set_kernel": ([C.c_void_p, C.c_int], C.c_int),
     "lbm_set_ghost_relaxation": ([C.c_void_p, C.c_double], C.c_int),
     "lbm_set_body_force": ([C.c_void_p, C.c_void_p, C.c_int, C.c_int], C.c_int),
+    "lbm_set_walls": ([C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "lbm_sync": ([C.c_void_p], C.c_int),
     "lbm_destroy": ([C.c_void_p], None),
     "lbm_last_error": ([], C.c_char_p),
@@ -175,6 +176,16 @@ class Lattice:
         shape = (3, self.nz, self.ny, self.nx)
         a = np.ascontiguousarray(np.broadcast_to(a.reshape(3, 1, 1, 1) if a.size == 3 else a, shape))
         _check(_lib.lbm_set_body_force(self._h, a.ctypes.data_as(C.c_void_p), 0, 0))
+
+    def set_walls(self, u_bottom=None, u_top=None, on=True):
+        """Walls normal to z half-way outside planes 0 and nz - 1 (half-way bounce-back), moving
+        with the tangential velocities u_bottom and u_top (3-vectors, default at rest); on=False
+        restores the periodic z direction.  Such a lattice steps with the two-pass kernel."""
+        if not on:
+            _check(_lib.lbm_set_walls(self._h, 0, None, None))
+            return
+        vec = lambda v: (C.c_double * 3)(*(np.zeros(3) if v is None else np.asarray(v, np.float64).reshape(3)))
+        _check(_lib.lbm_set_walls(self._h, 1, vec(u_bottom), vec(u_top)))
 
     def set_ghost_relaxation(self, tau_ghost):
         """Relaxation time of the non-hydrodynamic moments (Table I rows 11-19); tau_ghost = tau

@@ -31,7 +31,7 @@ def force_field(dims, seed, amp=2e-4):
 
 
 @pytest.mark.parametrize("dims", [(17, 9, 5), (32, 16, 1), (8, 6, 7)])
-@pytest.mark.parametrize("mode", ["thermal", "iso"])
+@pytest.mark.parametrize("mode", ["thermal", "iso", "standard"])
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
 def test_body_force_parity(dims, mode, storage, tol):
     tau, steps = 0.7, 30
@@ -98,9 +98,6 @@ def test_removing_the_force_restores_the_fused_step():
 
 def test_body_force_argument_errors():
     L = lbm()
-    s = L.Lattice(8, 8, 8, 0.7, storage="f32", mode="standard")
-    with pytest.raises(L.LBMError):
-        s.set_body_force([1e-4, 0, 0])
     g = L.Lattice(8, 8, 8, 0.7, storage="f32", kernel="fused")
     with pytest.raises(L.LBMError):
         g.set_body_force([1e-4, 0, 0])
