@@ -27,8 +27,10 @@ Also reported on the same JSON line:
   comparator    the standard lattice Boltzmann comparator (Sec. I, Eq. 4) timed on the same
                 input, the Galilean-invariance contrast measured on the GPU (shear-wave
                 viscosity in a moving frame, bump vs standard scheme), the MRT step's
-                throughput beside the single-rate two-pass step, and the body force (two-pass
-                throughput; Kolmogorov-flow amplitude against A / (T tau k^2));
+                throughput beside the single-rate two-pass step, the body force (two-pass
+                throughput; Kolmogorov-flow amplitude against A / (T tau k^2)), and the walls
+                (two-pass channel throughput; the gravity Couette flow of Sec. III C in two
+                frames, bump vs standard, against its closed form);
   cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded sample (a 48^3
                 Taylor-Green vortex for ~10 s).
 
@@ -377,6 +379,51 @@ def body_force(n=256, tau=0.55, mach=0.5, steps=100, N=64, T0=0.2, tau_k=0.6, A=
     return out
 
 
+def walls(n=256, tau=0.55, mach=0.5, steps=100, nz=32, T0=1.0 / 6.0, tau_c=0.8, ratio=2.0, U=0.02):
+    """Walls: the two-pass step of a 256^3 channel (walls at rest normal to z, a driving
+    acceleration along y) on the Taylor-Green input; and the gravity Couette flow of the paper's
+    Galilean test on the GPU, walls moving at (0, 2U) and at (-U, U) under a_z = -g with
+    g = ratio T / nz (density ratio e^ratio), in the bump scheme (prescribed T) and the standard
+    comparator, against the closed form u_y = (u_t - u_b)(1 - e^(g z'/T)) / (1 - e^(g H/T)) + u_b."""
+    import numpy as np
+    import torch
+    from paper_2501_00620_amd import lbm, workloads
+    rho, u, T = workloads.taylor_green(n, mach=mach)
+    lat = lbm.Lattice(n, n, n, tau, storage="f32")
+    lat.set_fields(rho, u, T)
+    lat.set_walls()
+    lat.set_body_force([0.0, 1e-5, 0.0])
+    secs = timed_steps(lat, steps, 5)
+    out = {"two_pass_mlups": n ** 3 * steps / secs / 1e6,
+           "workload": f"channel {n}^3 FP32 (Taylor-Green input, walls normal to z, uniform acceleration); "
+                       f"gravity Couette {nz} x 1 x 1, T {T0:.4g}, tau {tau_c}, density ratio e^{ratio:g}, "
+                       f"U {U}, {40 * nz * nz} steps"}
+    del lat
+    torch.cuda.empty_cache()
+    g = ratio * T0 / nz
+    zp = np.arange(nz) + 0.5
+    for mode in ("iso", "standard"):
+        prof = []
+        for ub, ut in ((0.0, 2 * U), (-U, U)):
+            exact = (ut - ub) * (1 - np.exp(g / T0 * zp)) / (1 - np.exp(g / T0 * nz)) + ub
+            r0 = np.exp(-g / T0 * zp)
+            u0 = np.zeros((3, nz, 1, 1))
+            u0[1, :, 0, 0] = exact
+            c = lbm.Lattice(1, 1, nz, tau_c, storage="f64", mode=mode)
+            c.set_fields((r0 / r0.mean()).reshape(nz, 1, 1), u0, np.full((nz, 1, 1), T0))
+            c.set_walls([0, ub, 0], [0, ut, 0])
+            c.set_body_force([0.0, 0.0, -g])
+            c.step(40 * nz * nz)
+            prof.append((c.moments()[1][1].cpu().numpy().reshape(nz), exact))
+        key = "bump" if mode == "iso" else "standard"
+        out[key] = {"max_err_over_2U": float(max(np.abs(p - e).max() for p, e in prof) / (2 * U)),
+                    "frame_difference_over_U": float(np.abs(prof[0][0] - U - prof[1][0]).max() / U)}
+    print(f"[bench] walls: two-pass channel {out['two_pass_mlups']:.0f} MLUPS; gravity Couette frame difference "
+          f"bump {out['bump']['frame_difference_over_U']:.3f} U, standard {out['standard']['frame_difference_over_U']:.3f} U",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def galilean_contrast(U=0.2, N=64, T0=1.0 / 3.0, tau=0.6, steps=2000, every=50):
     """The paper's Galilean-invariance contrast on the GPU: a shear wave u_y(x) on a background
     flow U along x decays with nu = T tau in the bump scheme and, by the standard scheme's third
@@ -532,7 +579,8 @@ def main():
         line["comparator"] = {"standard": run_standard(n, tau, mach, args.steps, args.warmup),
                               "galilean": galilean_contrast(),
                               "mrt": run_mrt(n, tau, mach, args.steps, args.warmup),
-                              "body_force": body_force()}
+                              "body_force": body_force(),
+                              "walls": walls()}
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     else:
         line["cpu_baseline"] = None
