@@ -123,6 +123,37 @@ def gradient(phi, axis):
     return out
 
 
+def projection_classes(dims):
+    """Classes of the D3Q19 populations that share their in-plane velocity, for a flow that does
+    not vary along z (dims=2: keys (e_x, e_y)) or along y and z (dims=1: keys e_x), in the order of
+    the projected layout.  Returns (classes, et2): a list of index arrays and |e_t|^2 per
+    population (the squared transverse speed)."""
+    e, _ = velocity_set()
+    if dims == 2:
+        keys = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (1, -1), (-1, 1), (-1, -1)]
+        classes = [np.flatnonzero((e[:, 0] == kx) & (e[:, 1] == ky)) for kx, ky in keys]
+        et2 = e[:, 2] ** 2
+    else:
+        classes = [np.flatnonzero(e[:, 0] == kx) for kx in (0, 1, -1)]
+        et2 = e[:, 1] ** 2 + e[:, 2] ** 2
+    return classes, et2
+
+
+def project(F, b, dims, thermal):
+    """A D3Q19 state of a flow without z (dims=2) or y, z (dims=1) dependence as class sums: F_c,
+    then (thermal) G_c = sum |e_t|^2 f over the classes with transverse members; b as xx yy xy [zz]
+    (dims=2) or xx [yy+zz] (dims=1).  F: (19, ...), b: (6, ...)."""
+    classes, et2 = projection_classes(dims)
+    Fp = [F[c].sum(axis=0) for c in classes]
+    if thermal:
+        Fp += [np.tensordot(et2[c], F[c], axes=1) for c in classes if et2[c].max() > 0]
+    if dims == 2:
+        bp = [b[0], b[1], b[3]] + ([b[2]] if thermal else [])
+    else:
+        bp = [b[0]] + ([b[1] + b[2]] if thermal else [])
+    return np.stack(Fp), np.stack(bp)
+
+
 # thermal: temperature from the total second moment; iso: prescribed temperature field;
 # standard: the standard lattice Boltzmann comparator (Sec. I, Eq. 4; no variance, prescribed T)
 MODES = {"thermal": 0, "iso": 1, "standard": 2}
