@@ -98,8 +98,8 @@ int lbm_step(lbm_handle h, long n_steps);
  * rho: n, u: 3n, T: n values of `dtype`.  Any pointer may be NULL to skip that field. */
 int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on_device);
 
-/* Checkpoint / parity: the post-stream state (fbar: 19n doubles, bbar: 6n doubles), decoded to
- * double.  lbm_set_state loads such a state (re-encoding it; codec scales are re-chosen for
+/* Checkpoint / parity: the post-stream state (fbar: 19n doubles, bbar: 6n doubles; on a projected
+ * lattice the nf and nb planes of lbm_get_projection, get only), decoded to double.  lbm_set_state loads such a state (re-encoding it; codec scales are re-chosen for
  * 16-bit storage).  get then set then step is bit-identical to stepping on for F64 and F32. */
 int lbm_get_state(lbm_handle h, void *F, void *b, int on_device);
 int lbm_set_state(lbm_handle h, const void *F, const void *b, int on_device);
@@ -162,6 +162,35 @@ int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device
  * periodic z direction.  Applies to every mode; a lattice with walls steps with the two-pass
  * kernel.  Errors: ARG (nz < 3, a normal or non-finite wall velocity, the fused kernel forced). */
 int lbm_set_walls(lbm_handle h, int on, const double *u_bottom, const double *u_top);
+
+/* Projected lattice (the lower-dimensional bump lattices that Sec. II B illustrates with D1Q3):
+ * the same step for flows that do not vary along z (dims = 2: nz = 1, a D2Q9 lattice) or along
+ * y and z (dims = 1: ny = nz = 1, D1Q3), held as class sums.  dims = 3 restores the D3Q19 layout.
+ * - Class sums: F_c = sum of the populations that share the in-plane velocity c.  In THERMAL
+ *   mode also G_c = the same sum weighted by |e_t|^2, the squared transverse speed.
+ * - Variance: the in-plane components of bbar; in THERMAL mode also the trace of its transverse
+ *   block.
+ * The step is exact: it reproduces the D3Q19 step of such a flow to rounding, since every
+ * update is linear per population and reads only moments the class sums carry.
+ * Per site the state is 12 values (D2Q9, ISO), 18 (D2Q9, THERMAL), 4 (D1Q3, ISO) or 8
+ * (D1Q3, THERMAL), in place of 25.  The call frees the state (set_fields again) and
+ * reallocates the buffers.
+ * Supports: modes THERMAL and ISO; storage F64 and F32; lbm_set_fields (the transverse velocity
+ * must be 0), lbm_step, lbm_get_moments (transverse u = 0), and lbm_get_state (see
+ * lbm_get_projection for its layout).  lbm_set_state, lbm_get_stored, lbm_invariants,
+ * lbm_health, walls, body force, a ghost rate and the fused kernel return ARG.
+ * Errors: ARG (dims, lattice shape, mode, storage, one of those settings), OOM, HIP. */
+int lbm_set_projection(lbm_handle h, int dims);
+
+/* The projection of a lattice and its lbm_get_state layout.
+ * - *dims: 3 (D3Q19), 2 or 1.
+ * - *nf: planes written to F; *nb: planes written to b.
+ * - Projected F holds the class sums F_c, then (THERMAL) the G_c of the classes with transverse
+ *   members.  D2Q9 classes: (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (1,-1) (-1,1) (-1,-1); the
+ *   first five have G.  D1Q3 classes: 0, +1, -1, all with G.
+ * - Projected b holds xx yy xy [zz] (D2Q9) or xx [yy+zz] (D1Q3).
+ * Any pointer may be NULL.  Errors: ARG (null handle). */
+int lbm_get_projection(lbm_handle h, int *dims, int *nf, int *nb);
 
 /* Block until all work queued on the lattice's stream is done. */
 int lbm_sync(lbm_handle h);

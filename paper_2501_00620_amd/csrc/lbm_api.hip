@@ -15,6 +15,7 @@
 #include "lbm_fused.hpp"
 #include "lbm_internal.hpp"
 #include "lbm_kernels.hpp"
+#include "lbm_proj.hpp"
 
 using namespace lbm;
 
@@ -130,6 +131,23 @@ template <typename Fn> int dispatch_storage(int storage, Fn &&fn) {
     return fail(LBM_ERR_ARG, "unknown storage %d", storage);
 }
 
+// Projected lattices (lbm_set_projection): F64 / F32 storage, D = 2 or 1, energy-conserving or not.
+template <typename Fn> int dispatch_proj(const lbm_lattice *h, Fn &&fn) {
+    using D2 = std::integral_constant<int, 2>;
+    using D1 = std::integral_constant<int, 1>;
+    const bool th = h->p.mode == LBM_THERMAL;
+    return dispatch_storage(h->p.storage, [&](auto SI) -> int {
+        constexpr int S = decltype(SI)::value;
+        if constexpr (S > 1) {
+            return fail(LBM_ERR_ARG, "projected lattices store F64 or F32");
+        } else {
+            if (h->proj == 2)
+                return th ? fn(SI, D2{}, std::true_type{}) : fn(SI, D2{}, std::false_type{});
+            return th ? fn(SI, D1{}, std::true_type{}) : fn(SI, D1{}, std::false_type{});
+        }
+    });
+}
+
 int check_launch() {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(LBM_ERR_HIP, "kernel launch: %s", hipGetErrorString(e));
@@ -215,6 +233,40 @@ template <int S> int step_fused(lbm_lattice *h) {
     h->cur = 1 - h->cur;
     h->gathered = false;
     return LBM_OK;
+}
+
+// One step of a projected lattice: in-plane predictor sources, then gradient, collision and the
+// push of the class sums.
+int step_proj(lbm_lattice *h) {
+    return dispatch_proj(h, [&](auto SI, auto DI, auto TI) -> int {
+        constexpr int S = decltype(SI)::value, D = decltype(DI)::value;
+        constexpr bool TH = decltype(TI)::value;
+        using T = typename Storage<S>::T;
+        using C = typename Storage<S>::C;
+        const Geo g = geo(h);
+        const StepConst<C> k = step_const<C>(h);
+        const T *F = (const T *)h->F[h->cur];
+        const T *B = (const T *)h->B[h->cur];
+        const dim3 grid(blocks_for(h->n)), block(BLOCK);
+        if (h->gathered) {
+            hipLaunchKernelGGL((k_proj_predict<S, D, TH, true>), grid, block, 0, h->stream, F, B, (C *)h->src,
+                               (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
+            hipLaunchKernelGGL((k_proj_collide<S, D, TH, true>), grid, block, 0, h->stream, F, B, (const C *)h->src,
+                               (T *)h->F[1 - h->cur], (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k,
+                               h->codec);
+        } else {
+            hipLaunchKernelGGL((k_proj_predict<S, D, TH, false>), grid, block, 0, h->stream, F, B, (C *)h->src,
+                               (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
+            hipLaunchKernelGGL((k_proj_collide<S, D, TH, false>), grid, block, 0, h->stream, F, B, (const C *)h->src,
+                               (T *)h->F[1 - h->cur], (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k,
+                               h->codec);
+        }
+        int rc = check_launch();
+        if (rc) return rc;
+        h->cur = 1 - h->cur;
+        h->gathered = false;
+        return LBM_OK;
+    });
 }
 
 // One step of the standard lattice Boltzmann comparator (Sec. I, Eq. 4): BGK and push.
@@ -322,6 +374,7 @@ void lbm_destroy(lbm_handle h) {
 
 int lbm_set_kernel(lbm_handle h, int kernel) {
     if (!h || kernel < 0 || kernel > 2) return fail(LBM_ERR_ARG, "bad kernel choice");
+    if (kernel == 2 && h->proj < 3) return fail(LBM_ERR_ARG, "projected lattices step with their own kernels");
     if (kernel == 2 && !fused_supported(geo(h), h->p.storage))
         return fail(LBM_ERR_ARG, "fused sweep does not support this lattice shape");
     if (kernel == 2 && h->tau_ghost > 0.0)
@@ -340,6 +393,7 @@ int lbm_set_walls(lbm_handle h, int on, const double *u_bottom, const double *u_
         return LBM_OK;
     }
     if (h->p.nz < 3) return fail(LBM_ERR_ARG, "walls need nz >= 3 (got %d)", h->p.nz);
+    if (h->proj < 3) return fail(LBM_ERR_ARG, "projected lattices have no walls");
     if (h->kernel == 2) return fail(LBM_ERR_ARG, "the fused sweep is periodic (lbm_set_kernel chose it)");
     double uw[6] = {0, 0, 0, 0, 0, 0};
     for (int c = 0; c < 3; c++) {
@@ -355,6 +409,71 @@ int lbm_set_walls(lbm_handle h, int on, const double *u_bottom, const double *u_
     return LBM_OK;
 }
 
+int lbm_set_projection(lbm_handle h, int dims) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (dims == h->proj) return LBM_OK;
+    if (dims != 1 && dims != 2 && dims != 3) return fail(LBM_ERR_ARG, "dims must be 1, 2 or 3");
+    if (dims == 2 && h->p.nz != 1) return fail(LBM_ERR_ARG, "a D2Q9 projection needs nz = 1");
+    if (dims == 1 && (h->p.ny != 1 || h->p.nz != 1)) return fail(LBM_ERR_ARG, "a D1Q3 projection needs ny = nz = 1");
+    if (dims < 3) {
+        if (h->p.mode == LBM_STANDARD) return fail(LBM_ERR_ARG, "the standard comparator is not projected");
+        if (h->p.storage != LBM_F64 && h->p.storage != LBM_F32)
+            return fail(LBM_ERR_ARG, "projected lattices store F64 or F32");
+        if (h->kernel == 2) return fail(LBM_ERR_ARG, "projected lattices step with their own two-pass kernels");
+        if (h->walls || h->accel || h->tau_ghost > 0.0)
+            return fail(LBM_ERR_ARG, "projected lattices have no walls, body force or ghost rate");
+    }
+    HIP_TRY(h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize());
+    for (int b = 0; b < 2; b++) {
+        if (h->F[b]) (void)hipFree(h->F[b]);
+        if (h->B[b]) (void)hipFree(h->B[b]);
+        h->F[b] = h->B[b] = nullptr;
+    }
+    if (h->src) (void)hipFree(h->src);
+    h->src = nullptr;
+    h->has_state = false;
+    h->proj = dims;
+    int nf = Q, nb = NB, nsrc = NSRC;
+    if (dims < 3) {
+        const bool th = h->p.mode == LBM_THERMAL;
+        nf = dims == 2 ? (th ? ProjLayout<2, true>::NF : ProjLayout<2, false>::NF)
+                       : (th ? ProjLayout<1, true>::NF : ProjLayout<1, false>::NF);
+        nb = dims == 2 ? (th ? ProjLayout<2, true>::NBP : ProjLayout<2, false>::NBP)
+                       : (th ? ProjLayout<1, true>::NBP : ProjLayout<1, false>::NBP);
+        nsrc = dims == 2 ? ProjSet<2>::NSP : ProjSet<1>::NSP;
+    }
+    const size_t sb = store_bytes(h->p.storage), n = h->n;
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < 2 && e == hipSuccess; b++) {
+        e = hipMalloc(&h->F[b], sb * nf * n);
+        if (e == hipSuccess) e = hipMalloc(&h->B[b], sb * nb * n);
+    }
+    // the two-pass and projected steps keep their source planes; the fused sweep needs none
+    if (e == hipSuccess && (dims < 3 || !fused_supported(geo(h), h->p.storage)))
+        e = hipMalloc(&h->src, compute_bytes(h->p.storage) * nsrc * n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? LBM_ERR_OOM : LBM_ERR_HIP, "allocation: %s", hipGetErrorString(e));
+    }
+    return LBM_OK;
+}
+
+int lbm_get_projection(lbm_handle h, int *dims, int *nf, int *nb) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    int f = Q, b = NB;
+    if (h->proj < 3) {
+        const bool th = h->p.mode == LBM_THERMAL;
+        f = h->proj == 2 ? (th ? ProjLayout<2, true>::NF : ProjLayout<2, false>::NF)
+                         : (th ? ProjLayout<1, true>::NF : ProjLayout<1, false>::NF);
+        b = h->proj == 2 ? (th ? ProjLayout<2, true>::NBP : ProjLayout<2, false>::NBP)
+                         : (th ? ProjLayout<1, true>::NBP : ProjLayout<1, false>::NBP);
+    }
+    if (dims) *dims = h->proj;
+    if (nf) *nf = f;
+    if (nb) *nb = b;
+    return LBM_OK;
+}
+
 int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     if (h->accel) {
@@ -364,6 +483,7 @@ int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device
     }
     if (!accel) return LBM_OK;
     if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_ARG, "unknown dtype %d", dtype);
+    if (h->proj < 3) return fail(LBM_ERR_ARG, "projected lattices have no body force");
     if (h->kernel == 2) return fail(LBM_ERR_ARG, "the fused sweep has no body force (lbm_set_kernel chose it)");
     const size_t count = 3 * (size_t)h->n, eb = dtype == LBM_DTYPE_F64 ? 8 : 4;
     HIP_TRY(hipMalloc(&h->accel, compute_bytes(h->p.storage) * count));
@@ -399,6 +519,7 @@ int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     if (!(tau_ghost > 0.0) || !std::isfinite(tau_ghost)) return fail(LBM_ERR_ARG, "tau_ghost must be > 0");
     if (h->p.mode == LBM_STANDARD) return fail(LBM_ERR_ARG, "the standard comparator relaxes with a single rate");
+    if (h->proj < 3 && tau_ghost != h->p.tau) return fail(LBM_ERR_ARG, "projected lattices relax with a single rate");
     if (h->kernel == 2 && tau_ghost != h->p.tau)
         return fail(LBM_ERR_ARG, "the fused sweep relaxes with a single rate (lbm_set_kernel chose it)");
     h->tau_ghost = tau_ghost == h->p.tau ? -1.0 : tau_ghost;
@@ -487,7 +608,23 @@ int lbm_set_fields(lbm_handle h, const void *rho, const void *u, const void *T, 
             }
         }
     }
-    if (!rc) {
+    if (!rc && h->proj < 3) {
+        rc = dispatch_proj(h, [&](auto SI, auto DI, auto TI) -> int {
+            constexpr int S = decltype(SI)::value, D = decltype(DI)::value;
+            constexpr bool TH = decltype(TI)::value;
+            using TT = typename Storage<S>::T;
+            using C = typename Storage<S>::C;
+            if (dtype == LBM_DTYPE_F64)
+                hipLaunchKernelGGL((k_proj_init<S, D, TH, double>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream,
+                                   (const double *)dr, (const double *)du, (const double *)dT, g, h->p.rho_ref,
+                                   h->p.T_ref, (TT *)h->F[0], (TT *)h->B[0], (C *)h->Tf, h->flag, h->codec);
+            else
+                hipLaunchKernelGGL((k_proj_init<S, D, TH, float>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream,
+                                   (const float *)dr, (const float *)du, (const float *)dT, g, h->p.rho_ref,
+                                   h->p.T_ref, (TT *)h->F[0], (TT *)h->B[0], (C *)h->Tf, h->flag, h->codec);
+            return check_launch();
+        });
+    } else if (!rc) {
         rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
             constexpr int S = decltype(SI)::value;
             using TT = typename Storage<S>::T;
@@ -519,6 +656,7 @@ int lbm_set_fields(lbm_handle h, const void *rho, const void *u, const void *T, 
     if (!rc) rc = read_clear_flag(h, &sat);
     if (stage) (void)hipFree(stage);
     if (rc) return rc;
+    if (h->proj < 3 && sat) return fail(LBM_ERR_ARG, "a projected lattice takes no transverse velocity");
     h->cur = 0;
     h->gathered = true;
     h->has_state = true;
@@ -536,12 +674,32 @@ int lbm_step(lbm_handle h, long n_steps) {
     for (long i = 0; i < n_steps; i++) {
         int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
             constexpr int S = decltype(SI)::value;
+            if (h->proj < 3) return step_proj(h);
             return standard ? step_std<S>(h) : fused ? step_fused<S>(h) : step_two_pass<S>(h);
         });
         if (rc) return rc;
         h->steps++;
     }
     return LBM_OK;
+}
+
+// Tail of lbm_get_moments: copy host outputs from the staging buffer, synchronise, free it.
+int finish_moments(lbm_lattice *h, int rc, void *rho, void *u, void *T, const char *dr, const char *du,
+                   const char *dT, size_t eb, void *stage, int on_device) {
+    const size_t n = h->n;
+    if (!rc && !on_device) {
+        hipError_t e = hipSuccess;
+        if (rho) e = hipMemcpyAsync(rho, dr, eb * n, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && u) e = hipMemcpyAsync(u, du, eb * 3 * n, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && T) e = hipMemcpyAsync(T, dT, eb * n, hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "copy of moments: %s", hipGetErrorString(e));
+    }
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "moments: %s", hipGetErrorString(e));
+    }
+    if (stage) (void)hipFree(stage);
+    return rc;
 }
 
 int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on_device) {
@@ -558,6 +716,36 @@ int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on
         dT = T ? (char *)stage + eb * 4 * n : nullptr;
     }
     const Geo g = geo(h);
+    if (h->proj < 3) {
+        int rc = dispatch_proj(h, [&](auto SI, auto DI, auto TI) -> int {
+            constexpr int S = decltype(SI)::value, D = decltype(DI)::value;
+            constexpr bool TH = decltype(TI)::value;
+            using TT = typename Storage<S>::T;
+            using C = typename Storage<S>::C;
+            const StepConst<C> k = step_const<C>(h);
+            const TT *F = (const TT *)h->F[h->cur];
+            const TT *B = (const TT *)h->B[h->cur];
+            const dim3 grid(blocks_for(h->n)), block(BLOCK);
+            auto launch = [&](auto GI, auto OI) {
+                constexpr bool G = decltype(GI)::value;
+                using OUT = typename decltype(OI)::type;
+                hipLaunchKernelGGL((k_proj_predict<S, D, TH, G>), grid, block, 0, h->stream, F, B, (C *)h->src,
+                                   (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
+                hipLaunchKernelGGL((k_proj_readout<S, D, TH, G, OUT>), grid, block, 0, h->stream, F, B,
+                                   (const C *)h->src, (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->p.T_ref,
+                                   (OUT *)dr, (OUT *)du, (OUT *)dT);
+            };
+            struct Dd { using type = double; };
+            struct Ff { using type = float; };
+            if (h->gathered) {
+                if (dtype == LBM_DTYPE_F64) launch(std::true_type{}, Dd{}); else launch(std::true_type{}, Ff{});
+            } else {
+                if (dtype == LBM_DTYPE_F64) launch(std::false_type{}, Dd{}); else launch(std::false_type{}, Ff{});
+            }
+            return check_launch();
+        });
+        return finish_moments(h, rc, rho, u, T, dr, du, dT, eb, stage, on_device);
+    }
     int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
         constexpr int S = decltype(SI)::value;
         using TT = typename Storage<S>::T;
@@ -592,19 +780,7 @@ int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on
         }
         return check_launch();
     });
-    if (!rc && !on_device) {
-        hipError_t e = hipSuccess;
-        if (rho) e = hipMemcpyAsync(rho, dr, eb * n, hipMemcpyDeviceToHost, h->stream);
-        if (e == hipSuccess && u) e = hipMemcpyAsync(u, du, eb * 3 * n, hipMemcpyDeviceToHost, h->stream);
-        if (e == hipSuccess && T) e = hipMemcpyAsync(T, dT, eb * n, hipMemcpyDeviceToHost, h->stream);
-        if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "copy of moments: %s", hipGetErrorString(e));
-    }
-    if (!rc) {
-        hipError_t e = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "moments: %s", hipGetErrorString(e));
-    }
-    if (stage) (void)hipFree(stage);
-    return rc;
+    return finish_moments(h, rc, rho, u, T, dr, du, dT, eb, stage, on_device);
 }
 
 int lbm_get_state(lbm_handle h, void *F, void *b, int on_device) {
@@ -619,7 +795,24 @@ int lbm_get_state(lbm_handle h, void *F, void *b, int on_device) {
         dB = b ? (double *)stage + Q * n : nullptr;
     }
     const Geo g = geo(h);
-    int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
+    int nf = Q, nbp = NB;
+    (void)lbm_get_projection(h, nullptr, &nf, &nbp);
+    int rc = h->proj < 3 ? dispatch_proj(h, [&](auto SI, auto DI, auto TI) -> int {
+        constexpr int S = decltype(SI)::value, D = decltype(DI)::value;
+        constexpr bool TH = decltype(TI)::value;
+        using TT = typename Storage<S>::T;
+        using C = typename Storage<S>::C;
+        const TT *Fs = (const TT *)h->F[h->cur];
+        const TT *Bs = (const TT *)h->B[h->cur];
+        const double th_ref = h->p.T_ref - 1.0 / 3.0;
+        if (h->gathered)
+            hipLaunchKernelGGL((k_proj_decode<S, D, TH, true>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream, Fs,
+                               Bs, g, h->codec, (C)h->p.rho_ref, th_ref, dF, dB);
+        else
+            hipLaunchKernelGGL((k_proj_decode<S, D, TH, false>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream, Fs,
+                               Bs, g, h->codec, (C)h->p.rho_ref, th_ref, dF, dB);
+        return check_launch();
+    }) : dispatch_storage(h->p.storage, [&](auto SI) -> int {
         constexpr int S = decltype(SI)::value;
         using TT = typename Storage<S>::T;
         using C = typename Storage<S>::C;
@@ -635,8 +828,8 @@ int lbm_get_state(lbm_handle h, void *F, void *b, int on_device) {
     });
     if (!rc && !on_device) {
         hipError_t e = hipSuccess;
-        if (F) e = hipMemcpyAsync(F, dF, sizeof(double) * Q * n, hipMemcpyDeviceToHost, h->stream);
-        if (e == hipSuccess && b) e = hipMemcpyAsync(b, dB, sizeof(double) * NB * n, hipMemcpyDeviceToHost, h->stream);
+        if (F) e = hipMemcpyAsync(F, dF, sizeof(double) * nf * n, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && b) e = hipMemcpyAsync(b, dB, sizeof(double) * nbp * n, hipMemcpyDeviceToHost, h->stream);
         if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "copy of state: %s", hipGetErrorString(e));
     }
     if (!rc) {
@@ -649,6 +842,7 @@ int lbm_get_state(lbm_handle h, void *F, void *b, int on_device) {
 
 int lbm_get_stored(lbm_handle h, void *F, void *b, int *b_is_gathered, int on_device) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (h->proj < 3) return fail(LBM_ERR_ARG, "not available on a projected lattice");
     if (!h->has_state) return fail(LBM_ERR_STATE, "no state");
     const size_t n = h->n;
     void *stage = nullptr;
@@ -683,6 +877,7 @@ int lbm_get_stored(lbm_handle h, void *F, void *b, int *b_is_gathered, int on_de
 
 int lbm_set_state(lbm_handle h, const void *F, const void *b, int on_device) {
     if (!h || !F || !b) return fail(LBM_ERR_ARG, "null argument");
+    if (h->proj < 3) return fail(LBM_ERR_ARG, "not available on a projected lattice");
     if ((h->p.mode == LBM_ISO || h->p.mode == LBM_STANDARD) && !h->has_state)
         return fail(LBM_ERR_STATE, "ISO and STANDARD mode: set_fields first (it provides the temperature field)");
     const size_t n = h->n;
@@ -753,6 +948,7 @@ int lbm_get_raw(lbm_handle h, void *F_codes, void *b_codes, int on_device) {
 
 int lbm_invariants(lbm_handle h, double out[5]) {
     if (!h || !out) return fail(LBM_ERR_ARG, "null argument");
+    if (h->proj < 3) return fail(LBM_ERR_ARG, "not available on a projected lattice");
     if (!h->has_state) return fail(LBM_ERR_STATE, "no state");
     const Geo g = geo(h);
     const int rb = red_blocks(h->n);
@@ -776,6 +972,7 @@ int lbm_invariants(lbm_handle h, double out[5]) {
 
 int lbm_health(lbm_handle h, long counts[2], double *max_u) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (h->proj < 3) return fail(LBM_ERR_ARG, "not available on a projected lattice");
     if (!h->has_state) return fail(LBM_ERR_STATE, "no state");
     const Geo g = geo(h);
     const int rb = red_blocks(h->n);

@@ -30,6 +30,7 @@ struct lbm_lattice {
     void *accel = nullptr;      // body-force acceleration, 3 planes of the compute type, or null
     int walls = 0;              // 1: walls normal to z bound the lattice (lbm_set_walls)
     double uw[6] = {0, 0, 0, 0, 0, 0};  // velocities of the bottom and top walls
+    int proj = 3;               // 3: D3Q19; 2, 1: the projected lattice of lbm_set_projection
 };
 
 namespace lbm {

@@ -1,0 +1,386 @@
+// lbm_proj.hpp -- projected lattices: the D3Q19 step (Sec. II C) for flows that do not vary along
+// z (D = 2, a D2Q9 lattice of nx x ny x 1 sites) or along y and z (D = 1, D1Q3, nx x 1 x 1), held
+// as sums over the classes of populations that share their in-plane velocity.
+//
+// Why this is exact.  On such a lattice the populations of one class stream to the same site and
+// the step's per-site update is linear in each population, with feq_i, Phi_i and the relaxation
+// targets depending only on moments: rho, j, the in-plane variance, the forcing moments and (the
+// energy-conserving mode) the trace of the second moment.  So the class sums
+//     F_c = sum_{i in c} fbar_i  and, for the temperature closure,  G_c = sum_{i in c} |e_i,t|^2 fbar_i
+// (e_t: the transverse part of e_i) evolve on their own, together with the in-plane components of
+// bbar and (energy-conserving mode) the trace of its transverse block.  Transverse velocities stay
+// zero and the transverse forcing moments vanish, as the lattice has no transverse gradient.
+//
+// Implementation.  A site's class sums are expanded into a canonical D3Q19 site -- the transverse
+// members of class c carry deviations proportional to their weights, alpha_c w_i with
+// alpha_c = dG_c / sum_{i in c} w_i |e_i,t|^2, the in-plane member the rest -- on which the D3Q19
+// per-site arithmetic (predictor_sources, collide) runs unchanged; the result is summed back into
+// classes.  The split cannot change the sums (the update is linear per population and reads
+// moments the split preserves).  The gradient is the D3Q19 stencil restricted to the plane (the
+// nine in-plane offsets for D = 2, the two x offsets for D = 1), which is what the D3Q19 stencil
+// reduces to when the transverse neighbours are the site's own column.
+//
+// Stored per site (deviations from the references, storage F64 or F32):
+//   F planes: dF_c for the NC classes, then dG_c for the NG classes with transverse members
+//             (energy-conserving mode only)
+//   B planes: the in-plane bbar deviations (D = 2: xx yy xy; D = 1: xx), then the transverse trace
+//             (energy-conserving mode only; D = 2: zz; D = 1: yy + zz)
+//   src     : the in-plane predictor sources (D = 2: R'xx R'yy R'xy u*x u*y; D = 1: R'xx u*x)
+// bbar is gathered or scattered exactly as on the D3Q19 lattice.
+#pragma once
+
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+template <int D> struct ProjSet;
+template <> struct ProjSet<2> {
+    static constexpr int NC = 9, NG = 5, NBI = 3, NSP = 5;
+    // class of each population: its (e_x, e_y) in the order of populations 0-4 and 7-10
+    static constexpr int CLS[Q] = {0, 1, 2, 3, 4, 0, 0, 5, 6, 7, 8, 1, 1, 3, 3, 2, 2, 4, 4};
+    static constexpr int CX[NC] = {0, 1, 0, -1, 0, 1, 1, -1, -1};
+    static constexpr int CY[NC] = {0, 0, 1, 0, -1, 1, -1, 1, -1};
+};
+template <> struct ProjSet<1> {
+    static constexpr int NC = 3, NG = 3, NBI = 1, NSP = 2;
+    static constexpr int CLS[Q] = {0, 1, 0, 2, 0, 0, 0, 1, 1, 2, 2, 1, 1, 2, 2, 0, 0, 0, 0};
+    static constexpr int CX[NC] = {0, 1, -1};
+    static constexpr int CY[NC] = {0, 0, 0};
+};
+
+// |e_i,t|^2, the squared transverse speed of population i
+template <int D> constexpr int et2(int i) { return D == 2 ? EZ[i] * EZ[i] : EY[i] * EY[i] + EZ[i] * EZ[i]; }
+// sum over class c of w_i, of w_i |e_i,t|^2, and of w_i over its transverse members
+template <int D> constexpr double class_w(int c) {
+    double s = 0.0;
+    for (int i = 0; i < Q; i++)
+        if (ProjSet<D>::CLS[i] == c) s += WQ[i];
+    return s;
+}
+template <int D> constexpr double class_gw(int c) {
+    double s = 0.0;
+    for (int i = 0; i < Q; i++)
+        if (ProjSet<D>::CLS[i] == c) s += WQ[i] * et2<D>(i);
+    return s;
+}
+template <int D> constexpr double class_tw(int c) {
+    double s = 0.0;
+    for (int i = 0; i < Q; i++)
+        if (ProjSet<D>::CLS[i] == c && et2<D>(i) > 0) s += WQ[i];
+    return s;
+}
+
+template <int D, bool TH> struct ProjLayout {
+    static constexpr int NF = ProjSet<D>::NC + (TH ? ProjSet<D>::NG : 0);
+    static constexpr int NBP = ProjSet<D>::NBI + (TH ? 1 : 0);
+};
+
+// Canonical D3Q19 site from class sums (dG = 0 without the energy-conserving mode).
+template <int D, bool TH, typename C>
+__device__ __forceinline__ void proj_expand(const C dF[ProjSet<D>::NC], const C *dG, const C bred[ProjLayout<D, TH>::NBP],
+                                            C d[Q], C beta[NB]) {
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int c = ProjSet<D>::CLS[I];
+        constexpr double tw = class_tw<D>(c);
+        if constexpr (tw == 0.0) {
+            d[I] = dF[c];
+        } else if constexpr (!TH) {
+            d[I] = et2<D>(I) > 0 ? C(0) : dF[c];
+        } else {
+            constexpr double inv_gw = 1.0 / class_gw<D>(c);
+            const C alpha = dG[c] * C(inv_gw);
+            if constexpr (et2<D>(I) > 0)
+                d[I] = alpha * C(WQ[I]);
+            else
+                d[I] = dF[c] - alpha * C(tw);
+        }
+    });
+#pragma unroll
+    for (int k = 0; k < NB; k++) beta[k] = C(0);
+    beta[0] = bred[0];
+    if constexpr (D == 2) {
+        beta[1] = bred[1];
+        beta[3] = bred[2];
+        if constexpr (TH) beta[2] = bred[3];
+    } else if constexpr (TH) {
+        beta[1] = beta[2] = C(0.5) * bred[1];
+    }
+}
+
+// Class sums of a D3Q19 site.
+template <int D, bool TH, typename C>
+__device__ __forceinline__ void proj_contract(const C d[Q], const C beta[NB], C dF[ProjSet<D>::NC], C *dG,
+                                              C bred[ProjLayout<D, TH>::NBP]) {
+#pragma unroll
+    for (int c = 0; c < ProjSet<D>::NC; c++) dF[c] = C(0);
+    if constexpr (TH) {
+#pragma unroll
+        for (int c = 0; c < ProjSet<D>::NG; c++) dG[c] = C(0);
+    }
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int c = ProjSet<D>::CLS[I];
+        dF[c] += d[I];
+        if constexpr (TH && et2<D>(I) > 0) dG[c] += C(et2<D>(I)) * d[I];
+    });
+    bred[0] = beta[0];
+    if constexpr (D == 2) {
+        bred[1] = beta[1];
+        bred[2] = beta[3];
+        if constexpr (TH) bred[3] = beta[2];
+    } else if constexpr (TH) {
+        bred[1] = beta[1] + beta[2];
+    }
+}
+
+// Neighbour of a site at in-plane offset (cx, cy).
+__device__ __forceinline__ int proj_at(const Nbr &nb, int cx, int cy) { return nb.at(cx, cy, 0); }
+
+// Load a site's class sums and its gathered bbar (Eq. 66 over classes: every member of class c
+// arrives from x - c), expanded.
+template <int S, int D, bool TH, bool GATHERED>
+__device__ __forceinline__ void proj_load(const typename Storage<S>::T *__restrict__ F,
+                                          const typename Storage<S>::T *__restrict__ B, size_t n, const Nbr &nb, int s,
+                                          const Codec &cd, typename Storage<S>::C rho_ref, typename Storage<S>::C d[Q],
+                                          typename Storage<S>::C beta[NB], PopMoments<typename Storage<S>::C> &m) {
+    using C = typename Storage<S>::C;
+    using PS = ProjSet<D>;
+    using PL = ProjLayout<D, TH>;
+    C dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP];
+#pragma unroll
+    for (int c = 0; c < PS::NC; c++) dF[c] = Storage<S>::load(F, (size_t)c * n + s, 0, cd);
+    if constexpr (TH) {
+#pragma unroll
+        for (int c = 0; c < PS::NG; c++) dG[c] = Storage<S>::load(F, (size_t)(PS::NC + c) * n + s, 0, cd);
+    }
+    if constexpr (GATHERED) {
+#pragma unroll
+        for (int k = 0; k < PL::NBP; k++) bred[k] = Storage<S>::load(B, (size_t)k * n + s, 0, cd);
+    } else {
+        C acc[PL::NBP], rho = rho_ref;
+#pragma unroll
+        for (int k = 0; k < PL::NBP; k++) acc[k] = C(0);
+        Unroll<0, PS::NC>::run([&](auto c) {
+            const int up = proj_at(nb, -PS::CX[c], -PS::CY[c]);
+            const C wgt = fma(C(class_w<D>(c)), rho_ref, dF[c]);
+            rho += dF[c];
+#pragma unroll
+            for (int k = 0; k < PL::NBP; k++) acc[k] += wgt * Storage<S>::load(B, (size_t)k * n + up, 0, cd);
+        });
+        const C inv = recip(rho);
+#pragma unroll
+        for (int k = 0; k < PL::NBP; k++) bred[k] = acc[k] * inv;
+    }
+    proj_expand<D, TH>(dF, dG, bred, d, beta);
+    m = pop_moments(d, rho_ref);
+}
+
+// In-plane gradient forcing moments from the reduced source planes.
+template <int D, typename C>
+__device__ __forceinline__ void proj_gradient(const C *__restrict__ src, size_t n, const Nbr &nb, C K, C F[3], C S[6]) {
+    GradAcc<C> acc;
+    grad_init(acc);
+    auto add = [&](auto I) {
+        const int at = proj_at(nb, EX[I], EY[I]);
+        C sv[NSRC];
+#pragma unroll
+        for (int c = 0; c < NSRC; c++) sv[c] = C(0);
+        if constexpr (D == 2) {
+            sv[0] = src[at];
+            sv[1] = src[n + at];
+            sv[3] = src[2 * n + at];
+            sv[6] = src[3 * n + at];
+            sv[7] = src[4 * n + at];
+        } else {
+            sv[0] = src[at];
+            sv[6] = src[n + at];
+        }
+        grad_add<C, decltype(I)::value>(acc, sv, K);
+    };
+    add(std::integral_constant<int, 1>{});
+    add(std::integral_constant<int, 3>{});
+    if constexpr (D == 2) {
+        add(std::integral_constant<int, 2>{});
+        add(std::integral_constant<int, 4>{});
+        add(std::integral_constant<int, 7>{});
+        add(std::integral_constant<int, 8>{});
+        add(std::integral_constant<int, 9>{});
+        add(std::integral_constant<int, 10>{});
+        grad_finish_thin(acc, F, S);
+    } else {
+        // each x face also stands for the four edges reading the same site (1/18 + 4/36 = 1/6);
+        // their transverse parts cancel
+#pragma unroll
+        for (int c = 0; c < 3; c++) F[c] = C(0);
+#pragma unroll
+        for (int c = 0; c < 6; c++) S[c] = C(0);
+        F[0] = -C(0.5) * acc.fF[0];
+        S[0] = -acc.fS[0];
+    }
+}
+
+// ---- pass A: predictor sources -------------------------------------------------------------------
+template <int S, int D, bool TH, bool GATHERED>
+__global__ void __launch_bounds__(BLOCK)
+k_proj_predict(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
+               typename Storage<S>::C *__restrict__ src, const typename Storage<S>::C *__restrict__ Tf,
+               typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd) {
+    using C = typename Storage<S>::C;
+    const int s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, z;
+    site_xyz(s, g, x, y, z);
+    const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    C d[Q], beta[NB];
+    PopMoments<C> m;
+    proj_load<S, D, TH, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, d, beta, m);
+    C o[NSRC];
+    predictor_sources(m, beta, site_T(Tf, Tconst, s), k, o);
+    const size_t n = g.n;
+    src[s] = o[0];
+    if constexpr (D == 2) {
+        src[n + s] = o[1];
+        src[2 * n + s] = o[3];
+        src[3 * n + s] = o[6];
+        src[4 * n + s] = o[7];
+    } else {
+        src[n + s] = o[6];
+    }
+}
+
+// ---- pass B: gradient, collision, push by class ----------------------------------------------------
+template <int S, int D, bool TH, bool GATHERED>
+__global__ void __launch_bounds__(BLOCK)
+k_proj_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
+               const typename Storage<S>::C *__restrict__ src, typename Storage<S>::T *__restrict__ Fo,
+               typename Storage<S>::T *__restrict__ Bo, const typename Storage<S>::C *__restrict__ Tf,
+               typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd) {
+    using C = typename Storage<S>::C;
+    using PS = ProjSet<D>;
+    using PL = ProjLayout<D, TH>;
+    const int s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, z;
+    site_xyz(s, g, x, y, z);
+    const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    C d[Q], beta[NB];
+    PopMoments<C> m;
+    proj_load<S, D, TH, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, d, beta, m);
+    C Fv[3], Sv[6];
+    proj_gradient<D>(src, g.n, nb, k.K, Fv, Sv);
+    collide(d, beta, m, Fv, Sv, site_T(Tf, Tconst, s), k);
+    C dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP];
+    proj_contract<D, TH>(d, beta, dF, dG, bred);
+    unsigned sat = 0;
+    Unroll<0, PS::NC>::run([&](auto c) {
+        const int to = proj_at(nb, PS::CX[c], PS::CY[c]);
+        Storage<S>::store(Fo, (size_t)c * g.n + to, 0, dF[c], cd, sat);
+        if constexpr (TH && c < PS::NG) Storage<S>::store(Fo, (size_t)(PS::NC + c) * g.n + to, 0, dG[c], cd, sat);
+    });
+#pragma unroll
+    for (int kk = 0; kk < PL::NBP; kk++) Storage<S>::store(Bo, (size_t)kk * g.n + s, 0, bred[kk], cd, sat);
+}
+
+// ---- readout of corrected moments (after k_proj_predict on the same state) ----------------------
+template <int S, int D, bool TH, bool GATHERED, typename OUT>
+__global__ void __launch_bounds__(BLOCK)
+k_proj_readout(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
+               const typename Storage<S>::C *__restrict__ src, const typename Storage<S>::C *__restrict__ Tf,
+               typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd, double T_ref,
+               OUT *__restrict__ rho, OUT *__restrict__ u, OUT *__restrict__ T) {
+    using C = typename Storage<S>::C;
+    const int s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, z;
+    site_xyz(s, g, x, y, z);
+    const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    C d[Q], beta[NB];
+    PopMoments<C> m;
+    proj_load<S, D, TH, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, d, beta, m);
+    C Fv[3], Sv[6];
+    proj_gradient<D>(src, g.n, nb, k.K, Fv, Sv);
+    C uc[3], Tc;
+    collide(d, beta, m, Fv, Sv, site_T(Tf, Tconst, s), k, uc, &Tc);
+    if (rho) rho[s] = (OUT)((double)k.rho_ref + (double)m.drho);
+    if (u) {
+        u[s] = (OUT)uc[0];
+        u[(size_t)g.n + s] = (OUT)uc[1];
+        u[2 * (size_t)g.n + s] = (OUT)uc[2];
+    }
+    if (T) T[s] = (OUT)(T_ref + (double)Tc);
+}
+
+// ---- initialisation: class sums of feq(rho, u) and the reduced beq(u, T) (gathered) -------------
+// Transverse velocity components must be zero; a site with one sets *flag.
+template <int S, int D, bool TH, typename IN>
+__global__ void __launch_bounds__(BLOCK)
+k_proj_init(const IN *__restrict__ rho, const IN *__restrict__ u, const IN *__restrict__ T, Geo g, double rho_ref,
+            double T_ref, typename Storage<S>::T *__restrict__ F, typename Storage<S>::T *__restrict__ B,
+            typename Storage<S>::C *__restrict__ Tf, unsigned *__restrict__ flag, Codec cd) {
+    using C = typename Storage<S>::C;
+    using PS = ProjSet<D>;
+    using PL = ProjLayout<D, TH>;
+    const int s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= g.n) return;
+    const size_t n = g.n;
+    const double r = (double)rho[s], ux = (double)u[s], uy = (double)u[n + s], uz = (double)u[2 * n + s];
+    if (uz != 0.0 || (D == 1 && uy != 0.0)) *flag = 2u;
+    const double theta = (double)T[s] - T_ref;
+    double f[Q], b[NB];
+    equilibrium_dev(r - rho_ref, r, ux, D == 2 ? uy : 0.0, 0.0, f);
+    variance_eq_dev(ux, D == 2 ? uy : 0.0, 0.0, theta, b);
+    double dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP];
+    proj_contract<D, TH>(f, b, dF, dG, bred);
+    unsigned sat = 0;
+#pragma unroll
+    for (int c = 0; c < PS::NC; c++) Storage<S>::store(F, (size_t)c * n + s, 0, (C)dF[c], cd, sat);
+    if constexpr (TH) {
+#pragma unroll
+        for (int c = 0; c < PS::NG; c++) Storage<S>::store(F, (size_t)(PS::NC + c) * n + s, 0, (C)dG[c], cd, sat);
+    }
+#pragma unroll
+    for (int kk = 0; kk < PL::NBP; kk++) Storage<S>::store(B, (size_t)kk * n + s, 0, (C)bred[kk], cd, sat);
+    if (Tf) Tf[s] = (C)theta;
+}
+
+// ---- decoded state in FP64: full class sums and gathered reduced bbar ----------------------------
+template <int S, int D, bool TH, bool GATHERED>
+__global__ void __launch_bounds__(BLOCK)
+k_proj_decode(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B, Geo g,
+              Codec cd, typename Storage<S>::C rho_ref, double theta_ref, double *__restrict__ Fout,
+              double *__restrict__ Bout) {
+    using C = typename Storage<S>::C;
+    using PS = ProjSet<D>;
+    using PL = ProjLayout<D, TH>;
+    const int s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= g.n) return;
+    int x, y, z;
+    site_xyz(s, g, x, y, z);
+    const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+    C d[Q], beta[NB];
+    PopMoments<C> m;
+    proj_load<S, D, TH, GATHERED>(F, B, g.n, nb, s, cd, rho_ref, d, beta, m);
+    C dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP];
+    proj_contract<D, TH>(d, beta, dF, dG, bred);
+    const size_t n = g.n;
+    if (Fout) {
+        Unroll<0, PS::NC>::run([&](auto c) {
+            Fout[(size_t)c * n + s] = class_w<D>(c) * (double)rho_ref + (double)dF[c];
+            if constexpr (TH && c < PS::NG)
+                Fout[(size_t)(PS::NC + c) * n + s] = class_gw<D>(c) * (double)rho_ref + (double)dG[c];
+        });
+    }
+    if (Bout) {
+        // references: theta_ref on each in-plane diagonal, 0 off the diagonal; the transverse
+        // trace holds 3 - D diagonal components
+        Bout[s] = theta_ref + (double)bred[0];
+        if constexpr (D == 2) {
+            Bout[n + s] = theta_ref + (double)bred[1];
+            Bout[2 * n + s] = (double)bred[2];
+            if constexpr (TH) Bout[3 * n + s] = theta_ref + (double)bred[3];
+        } else if constexpr (TH) {
+            Bout[n + s] = 2.0 * theta_ref + (double)bred[1];
+        }
+    }
+}
+
+}  // namespace lbm

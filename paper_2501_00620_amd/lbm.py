@@ -53,6 +53,8 @@ SIGNATURES = {
     "lbm_set_ghost_relaxation": ([C.c_void_p, C.c_double], C.c_int),
     "lbm_set_body_force": ([C.c_void_p, C.c_void_p, C.c_int, C.c_int], C.c_int),
     "lbm_set_walls": ([C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+    "lbm_set_projection": ([C.c_void_p, C.c_int], C.c_int),
+    "lbm_get_projection": ([C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "lbm_sync": ([C.c_void_p], C.c_int),
     "lbm_destroy": ([C.c_void_p], None),
     "lbm_last_error": ([], C.c_char_p),
@@ -227,10 +229,23 @@ class Lattice:
                                     C.c_void_p(T.data_ptr()), 0 if dt == torch.float64 else 1, 1))
         return rho, u, T
 
+    def projection(self):
+        """(dims, nf, nb): 3 for D3Q19, else the projected lattice and its state planes."""
+        d, f, b = C.c_int(), C.c_int(), C.c_int()
+        _check(_lib.lbm_get_projection(self._h, C.byref(d), C.byref(f), C.byref(b)))
+        return d.value, f.value, b.value
+
+    def set_projection(self, dims):
+        """Hold the lattice as a projected D2Q9 (dims=2, nz = 1) or D1Q3 (dims=1, ny = nz = 1)
+        lattice of class sums, or as D3Q19 (dims=3).  Call before set_fields."""
+        _check(_lib.lbm_set_projection(self._h, int(dims)))
+
     def get_state(self):
+        """(F, b) in float64: 19 + 6 planes, or on a projected lattice the planes of projection()."""
         torch = _torch()
-        F = torch.empty((19,) + self.shape, dtype=torch.float64, device="cuda")
-        b = torch.empty((6,) + self.shape, dtype=torch.float64, device="cuda")
+        _, nf, nb = self.projection()
+        F = torch.empty((nf,) + self.shape, dtype=torch.float64, device="cuda")
+        b = torch.empty((nb,) + self.shape, dtype=torch.float64, device="cuda")
         self._sync_torch()
         _check(_lib.lbm_get_state(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(b.data_ptr()), 1))
         return F, b
