@@ -424,6 +424,47 @@ def walls(n=256, tau=0.55, mach=0.5, steps=100, nz=32, T0=1.0 / 6.0, tau_c=0.8, 
     return out
 
 
+# Algorithmic bytes per site update of the projected one-launch step, FP32: the state read once
+# and written once (12 values per site D2Q9 ISO, 18 THERMAL, 4 D1Q3 ISO, 8 THERMAL).
+PROJ_BYTES = {(2, "iso"): 2 * 4 * 12, (2, "thermal"): 2 * 4 * 18, (1, "iso"): 2 * 4 * 4, (1, "thermal"): 2 * 4 * 8}
+
+
+def projections(n2=4096, n1=1 << 24, tau=0.6, steps=200):
+    """Projected lattices against the D3Q19 layout on the same planar (n2 x n2 x 1) and linear
+    (n1 x 1 x 1) lattices, FP32, random smooth fields without transverse velocity: MLUPS of each,
+    GB/s of the projected step (PROJ_BYTES), and the largest relative difference of the moments
+    after the timed steps (the two layouts compute the same step)."""
+    import numpy as np
+    import torch
+    from paper_2501_00620_amd import lbm, workloads
+    out = {"workload": f"planar {n2} x {n2} x 1 and linear {n1} x 1 x 1, FP32, tau {tau}, {steps} steps"}
+    for dims, shape in ((2, (n2, n2)), (1, (n1, 1))):
+        rho, u, T = workloads.fourier_fields(shape[0], shape[1], 1, seed=7, u_max=0.1)
+        u = np.array(u)
+        u[2] = 0.0
+        if dims == 1:
+            u[1] = 0.0
+        for mode in ("iso", "thermal"):
+            rec = {}
+            mom = []
+            for proj in (3, dims):
+                lat = lbm.Lattice(shape[0], shape[1], 1, tau, storage="f32", mode=mode)
+                lat.set_projection(proj)
+                lat.set_fields(rho, u, T)
+                secs = timed_steps(lat, steps, 5)
+                rec["d3q19_mlups" if proj == 3 else "projected_mlups"] = shape[0] * shape[1] * steps / secs / 1e6
+                mom.append([q.double() for q in lat.moments()])
+                del lat
+                torch.cuda.empty_cache()
+            rec["projected_GBps"] = rec["projected_mlups"] * PROJ_BYTES[(dims, mode)] / 1e3
+            rec["speedup"] = rec["projected_mlups"] / rec["d3q19_mlups"]
+            rec["max_rel_diff"] = max(rel_l2(a, b) for a, b in zip(mom[1], mom[0]))
+            out[f"{'d2q9' if dims == 2 else 'd1q3'}_{mode}"] = rec
+            print(f"[bench] {'D2Q9' if dims == 2 else 'D1Q3'} {mode}: {rec['projected_mlups']:.0f} MLUPS "
+                  f"({rec['projected_GBps']:.0f} GB/s) vs D3Q19 {rec['d3q19_mlups']:.0f}", file=sys.stderr, flush=True)
+    return out
+
+
 def galilean_contrast(U=0.2, N=64, T0=1.0 / 3.0, tau=0.6, steps=2000, every=50):
     """The paper's Galilean-invariance contrast on the GPU: a shear wave u_y(x) on a background
     flow U along x decays with nu = T tau in the bump scheme and, by the standard scheme's third
@@ -581,6 +622,7 @@ def main():
                               "mrt": run_mrt(n, tau, mach, args.steps, args.warmup),
                               "body_force": body_force(),
                               "walls": walls()}
+        line["projections"] = projections()
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     else:
         line["cpu_baseline"] = None

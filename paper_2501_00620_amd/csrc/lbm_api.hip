@@ -248,7 +248,18 @@ int step_proj(lbm_lattice *h) {
         const T *F = (const T *)h->F[h->cur];
         const T *B = (const T *)h->B[h->cur];
         const dim3 grid(blocks_for(h->n)), block(BLOCK);
-        if (h->gathered) {
+        if (h->kernel != 1) {  // one launch per step (lbm_set_kernel(1) keeps the two-pass form)
+            using TL = ProjTile<D>;
+            const dim3 tiles((h->p.nx + TL::TX - 1) / TL::TX, (h->p.ny + TL::TY - 1) / TL::TY);
+            T *Fo = (T *)h->F[1 - h->cur];
+            T *Bo = (T *)h->B[1 - h->cur];
+            if (h->gathered)
+                hipLaunchKernelGGL((k_proj_fused<S, D, TH, true>), tiles, dim3(TL::NT), 0, h->stream, F, B, Fo, Bo,
+                                   (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
+            else
+                hipLaunchKernelGGL((k_proj_fused<S, D, TH, false>), tiles, dim3(TL::NT), 0, h->stream, F, B, Fo, Bo,
+                                   (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
+        } else if (h->gathered) {
             hipLaunchKernelGGL((k_proj_predict<S, D, TH, true>), grid, block, 0, h->stream, F, B, (C *)h->src,
                                (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
             hipLaunchKernelGGL((k_proj_collide<S, D, TH, true>), grid, block, 0, h->stream, F, B, (const C *)h->src,

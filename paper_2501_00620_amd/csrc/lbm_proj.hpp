@@ -280,6 +280,150 @@ k_proj_collide(const typename Storage<S>::T *__restrict__ F, const typename Stor
     for (int kk = 0; kk < PL::NBP; kk++) Storage<S>::store(Bo, (size_t)kk * g.n + s, 0, bred[kk], cd, sat);
 }
 
+// ---- one-launch step: sources of a tile and its one-site halo in LDS -------------------------------
+// A work-group owns a TX x TY tile (D = 2: 32 x 8; D = 1: 256 x 1).  Phase 1 computes the in-plane
+// predictor sources of the tile and its one-site ring (periodic wrap) into LDS; phase 2 takes each
+// owned site's gradient from LDS, collides it and pushes its class sums.  The ring's sources are
+// recomputed by the neighbouring tiles (1.3x the source work for D = 2), and the reads they need
+// mostly hit in L2; the state goes through HBM once each way.
+template <int D> struct ProjTile {
+    static constexpr int TX = D == 2 ? 32 : 256, TY = D == 2 ? 8 : 1, HY = D == 2 ? 1 : 0;
+    static constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2 * HY, HN = LX * LY;
+    static constexpr int NRING = HN - NT;  // D = 2: two rows of LX and two columns of TY
+};
+
+// LDS slot of ring site r: the top and bottom rows, then the left and right columns (D = 2), or
+// the two ends of the row (D = 1).
+template <int D> __device__ __forceinline__ int proj_ring_slot(int r) {
+    using TL = ProjTile<D>;
+    if constexpr (D == 1) {
+        return r == 0 ? 0 : TL::LX - 1;
+    } else {
+        if (r < TL::LX) return r;
+        if (r < 2 * TL::LX) return (TL::LY - 1) * TL::LX + (r - TL::LX);
+        r -= 2 * TL::LX;
+        const int j = 1 + (r >> 1);
+        return j * TL::LX + ((r & 1) ? TL::LX - 1 : 0);
+    }
+}
+
+// Sources of the site held in LDS slot l of the tile at (x0, y0), periodic; false if the slot
+// wraps beyond a lattice smaller than the ring (such slots are never read).
+template <int S, int D, bool TH, bool GATHERED>
+__device__ __forceinline__ bool proj_tile_site(const typename Storage<S>::T *__restrict__ F,
+                                               const typename Storage<S>::T *__restrict__ B,
+                                               const typename Storage<S>::C *__restrict__ Tf,
+                                               typename Storage<S>::C Tconst, const Geo &g,
+                                               const StepConst<typename Storage<S>::C> &k, const Codec &cd, int x0,
+                                               int y0, int l, typename Storage<S>::C (*lsrc)[ProjTile<D>::HN],
+                                               typename Storage<S>::C d[Q], typename Storage<S>::C beta[NB],
+                                               PopMoments<typename Storage<S>::C> &m) {
+    using C = typename Storage<S>::C;
+    using TL = ProjTile<D>;
+    const int i = l % TL::LX, j = l / TL::LX;
+    int x = x0 - 1 + i, y = y0 - TL::HY + j;
+    x = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
+    y = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
+    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) return false;
+    const int s = y * g.nx + x;
+    const Nbr nb = make_nbr(x, y, 0, g.nx, g.ny, 1);
+    proj_load<S, D, TH, GATHERED>(F, B, (size_t)g.n, nb, s, cd, k.rho_ref, d, beta, m);
+    C o[NSRC];
+    predictor_sources(m, beta, site_T(Tf, Tconst, s), k, o);
+    lsrc[0][l] = o[0];
+    if constexpr (D == 2) {
+        lsrc[1][l] = o[1];
+        lsrc[2][l] = o[3];
+        lsrc[3][l] = o[6];
+        lsrc[4][l] = o[7];
+    } else {
+        lsrc[1][l] = o[6];
+    }
+    return true;
+}
+
+template <int S, int D, bool TH, bool GATHERED>
+__global__ void __launch_bounds__(ProjTile<D>::NT)
+k_proj_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
+             typename Storage<S>::T *__restrict__ Fo, typename Storage<S>::T *__restrict__ Bo,
+             const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
+             StepConst<typename Storage<S>::C> k, Codec cd) {
+    using C = typename Storage<S>::C;
+    using PS = ProjSet<D>;
+    using PL = ProjLayout<D, TH>;
+    using TL = ProjTile<D>;
+    __shared__ C lsrc[PS::NSP][TL::HN];
+    const int x0 = blockIdx.x * TL::TX, y0 = blockIdx.y * TL::TY;
+    const size_t n = g.n;
+    const int tx = threadIdx.x % TL::TX, ty = threadIdx.x / TL::TX;
+    // phase 1: the owned slot (its state stays in registers for phase 2), then the ring
+    C d[Q], beta[NB];
+    PopMoments<C> m;
+    (void)proj_tile_site<S, D, TH, GATHERED>(F, B, Tf, Tconst, g, k, cd, x0, y0,
+                                             (ty + TL::HY) * TL::LX + tx + 1, lsrc, d, beta, m);
+    for (int r = threadIdx.x; r < TL::NRING; r += TL::NT) {
+        C d2[Q], beta2[NB];
+        PopMoments<C> m2;
+        (void)proj_tile_site<S, D, TH, GATHERED>(F, B, Tf, Tconst, g, k, cd, x0, y0, proj_ring_slot<D>(r), lsrc, d2,
+                                                 beta2, m2);
+    }
+    __syncthreads();
+    // phase 2: the owned site
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= g.nx || y >= g.ny) return;
+    const int s = y * g.nx + x;
+    const Nbr nb = make_nbr(x, y, 0, g.nx, g.ny, 1);
+    GradAcc<C> acc;
+    grad_init(acc);
+    auto add = [&](auto I) {
+        constexpr int ex = EX[decltype(I)::value], ey = EY[decltype(I)::value];
+        const int l = (ty + TL::HY + ey) * TL::LX + (tx + 1 + ex);
+        C sv[NSRC];
+#pragma unroll
+        for (int c = 0; c < NSRC; c++) sv[c] = C(0);
+        sv[0] = lsrc[0][l];
+        if constexpr (D == 2) {
+            sv[1] = lsrc[1][l];
+            sv[3] = lsrc[2][l];
+            sv[6] = lsrc[3][l];
+            sv[7] = lsrc[4][l];
+        } else {
+            sv[6] = lsrc[1][l];
+        }
+        grad_add<C, decltype(I)::value>(acc, sv, k.K);
+    };
+    C Fv[3], Sv[6];
+    add(std::integral_constant<int, 1>{});
+    add(std::integral_constant<int, 3>{});
+    if constexpr (D == 2) {
+        add(std::integral_constant<int, 2>{});
+        add(std::integral_constant<int, 4>{});
+        add(std::integral_constant<int, 7>{});
+        add(std::integral_constant<int, 8>{});
+        add(std::integral_constant<int, 9>{});
+        add(std::integral_constant<int, 10>{});
+        grad_finish_thin(acc, Fv, Sv);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; c++) Fv[c] = C(0);
+#pragma unroll
+        for (int c = 0; c < 6; c++) Sv[c] = C(0);
+        Fv[0] = -C(0.5) * acc.fF[0];
+        Sv[0] = -acc.fS[0];
+    }
+    collide(d, beta, m, Fv, Sv, site_T(Tf, Tconst, s), k);
+    C dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP];
+    proj_contract<D, TH>(d, beta, dF, dG, bred);
+    unsigned sat = 0;
+    Unroll<0, PS::NC>::run([&](auto c) {
+        const int to = proj_at(nb, PS::CX[c], PS::CY[c]);
+        Storage<S>::store(Fo, (size_t)c * n + to, 0, dF[c], cd, sat);
+        if constexpr (TH && c < PS::NG) Storage<S>::store(Fo, (size_t)(PS::NC + c) * n + to, 0, dG[c], cd, sat);
+    });
+#pragma unroll
+    for (int kk = 0; kk < PL::NBP; kk++) Storage<S>::store(Bo, (size_t)kk * n + s, 0, bred[kk], cd, sat);
+}
+
 // ---- readout of corrected moments (after k_proj_predict on the same state) ----------------------
 template <int S, int D, bool TH, bool GATHERED, typename OUT>
 __global__ void __launch_bounds__(BLOCK)

@@ -80,6 +80,24 @@ def test_projection_equals_the_d3q19_step_on_gpu(dims, shape, mode):
         assert rel_l2(a, b) <= 1e-13
 
 
+@pytest.mark.parametrize("dims,shape", [(2, (70, 33)), (2, (5, 3)), (1, (300, 1)), (1, (3, 1))])
+@pytest.mark.parametrize("mode", ["thermal", "iso"])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-14), ("f32", 1e-6)])
+def test_one_launch_step_equals_the_two_pass_step(dims, shape, mode, storage, tol):
+    # tiles with a ragged edge, and lattices smaller than one tile (the ring wraps more than once)
+    nx, ny = shape
+    fields = planar_fields(nx, ny, seed=43)
+    out = []
+    for kernel in ("auto", "two_pass"):
+        g = lbm().Lattice(nx, ny, 1, 0.7, storage=storage, mode=mode, kernel=kernel)
+        g.set_projection(dims)
+        g.set_fields(*fields)
+        g.step(25)
+        out.append([q.cpu().numpy() for q in g.get_state()])
+    for a, b in zip(*out):
+        assert rel_l2(a, b) <= tol
+
+
 def test_sod_tube_as_d1q3():
     # the Sod configuration of the D3Q19 tests: 400 x 1 x 1, 1000 steps, FP64
     rho, u, T = wl.sod(400)
