@@ -281,13 +281,19 @@ k_proj_collide(const typename Storage<S>::T *__restrict__ F, const typename Stor
 }
 
 // ---- one-launch step: sources of a tile and its one-site halo in LDS -------------------------------
-// A work-group owns a TX x TY tile (D = 2: 32 x 8; D = 1: 256 x 1).  Phase 1 computes the in-plane
+// A work-group owns a TX x TY tile (D = 2: 128 x 8; D = 1: 256 x 1).  Phase 1 computes the in-plane
 // predictor sources of the tile and its one-site ring (periodic wrap) into LDS; phase 2 takes each
 // owned site's gradient from LDS, collides it and pushes its class sums.  The ring's sources are
-// recomputed by the neighbouring tiles (1.3x the source work for D = 2), and the reads they need
+// recomputed by the neighbouring tiles (1.27x the source work for D = 2), and the reads they need
 // mostly hit in L2; the state goes through HBM once each way.
+#ifndef PROJ2_TX
+#define PROJ2_TX 128
+#endif
+#ifndef PROJ2_TY
+#define PROJ2_TY 8
+#endif
 template <int D> struct ProjTile {
-    static constexpr int TX = D == 2 ? 32 : 256, TY = D == 2 ? 8 : 1, HY = D == 2 ? 1 : 0;
+    static constexpr int TX = D == 2 ? PROJ2_TX : 256, TY = D == 2 ? PROJ2_TY : 1, HY = D == 2 ? 1 : 0;
     static constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2 * HY, HN = LX * LY;
     static constexpr int NRING = HN - NT;  // D = 2: two rows of LX and two columns of TY
 };
