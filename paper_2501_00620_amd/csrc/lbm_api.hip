@@ -199,17 +199,26 @@ template <int S> int step_two_pass(lbm_lattice *h) {
     const C *Tf = (const C *)h->Tf;
     const C Tc = (C)h->Tconst;
     const dim3 grid(blocks_for(h->n)), block(BLOCK);
-    auto launch = [&](auto GI, auto MI, auto WI) {
+    auto collide = [&](auto GI, auto MI, auto WI, int s0, int count) {
         constexpr bool G = decltype(GI)::value, M = decltype(MI)::value, W = decltype(WI)::value;
-        hipLaunchKernelGGL((k_predict<S, G>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k, h->codec);
-        hipLaunchKernelGGL((k_collide<S, G, M, W>), grid, block, 0, h->stream, F, B, src, Fo, Bo, Tf, Tc, g, k,
-                           h->codec, h->flag, (const C *)h->accel);
+        hipLaunchKernelGGL((k_collide<S, G, M, W>), dim3(blocks_for(count)), block, 0, h->stream, F, B, src, Fo, Bo,
+                           Tf, Tc, g, k, h->codec, h->flag, (const C *)h->accel, s0, count);
     };
-    auto with_walls = [&](auto GI, auto MI) {
-        if (h->walls) launch(GI, MI, std::true_type{}); else launch(GI, MI, std::false_type{});
+    auto launch = [&](auto GI, auto MI) {
+        hipLaunchKernelGGL((k_predict<S, decltype(GI)::value>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k,
+                           h->codec);
+        if (!h->walls) {
+            collide(GI, MI, std::false_type{}, 0, h->n);
+        } else {
+            // interior planes with the periodic kernel; the two wall planes with the wall kernel
+            const int nxy = h->p.nx * h->p.ny;
+            collide(GI, MI, std::false_type{}, nxy, (h->p.nz - 2) * nxy);
+            collide(GI, MI, std::true_type{}, 0, nxy);
+            collide(GI, MI, std::true_type{}, (h->p.nz - 1) * nxy, nxy);
+        }
     };
     auto with_mrt = [&](auto GI) {
-        if (h->tau_ghost > 0.0) with_walls(GI, std::true_type{}); else with_walls(GI, std::false_type{});
+        if (h->tau_ghost > 0.0) launch(GI, std::true_type{}); else launch(GI, std::false_type{});
     };
     if (h->gathered) with_mrt(std::true_type{}); else with_mrt(std::false_type{});
     int rc = check_launch();
@@ -284,12 +293,19 @@ int step_proj(lbm_lattice *h) {
 template <int S> int step_std(lbm_lattice *h) {
     using T = typename Storage<S>::T;
     using C = typename Storage<S>::C;
-    auto launch = [&](auto WI) {
-        hipLaunchKernelGGL((k_std<S, decltype(WI)::value>), dim3(blocks_for(h->n)), dim3(BLOCK), 0, h->stream,
+    auto launch = [&](auto WI, int s0, int count) {
+        hipLaunchKernelGGL((k_std<S, decltype(WI)::value>), dim3(blocks_for(count)), dim3(BLOCK), 0, h->stream,
                            (const T *)h->F[h->cur], (T *)h->F[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, geo(h),
-                           step_const<C>(h), h->codec, h->flag, (const C *)h->accel);
+                           step_const<C>(h), h->codec, h->flag, (const C *)h->accel, s0, count);
     };
-    if (h->walls) launch(std::true_type{}); else launch(std::false_type{});
+    if (!h->walls) {
+        launch(std::false_type{}, 0, h->n);
+    } else {  // interior planes with the periodic kernel, the two wall planes with the wall kernel
+        const int nxy = h->p.nx * h->p.ny;
+        launch(std::false_type{}, nxy, (h->p.nz - 2) * nxy);
+        launch(std::true_type{}, 0, nxy);
+        launch(std::true_type{}, (h->p.nz - 1) * nxy, nxy);
+    }
     int rc = check_launch();
     if (rc) return rc;
     // bbar carries nothing in this model: both buffers hold its reference (zero deviation) since

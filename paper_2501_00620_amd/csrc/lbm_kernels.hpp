@@ -147,17 +147,19 @@ __device__ __forceinline__ void gradient_from_src(const C *__restrict__ src, siz
 
 // ---- pass B: gradients, collision, push-stream ------------------------------------------------
 // MRT: the non-hydrodynamic moments relax at their own rate (ghost_relax).  WALLS: the lattice
-// has walls (the periodic instantiation carries no wall code).
+// has walls (the periodic instantiation carries no wall code; on a lattice with walls it serves
+// the interior planes, which no wall touches).  The launch covers sites s0 .. s0 + count - 1.
 template <int S, bool GATHERED, bool MRT = false, bool WALLS = false>
 __global__ void __launch_bounds__(BLOCK)
 k_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
           const typename Storage<S>::C *__restrict__ src, typename Storage<S>::T *__restrict__ Fo,
           typename Storage<S>::T *__restrict__ Bo, const typename Storage<S>::C *__restrict__ Tf,
           typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd,
-          unsigned *__restrict__ flag, const typename Storage<S>::C *__restrict__ accel) {
+          unsigned *__restrict__ flag, const typename Storage<S>::C *__restrict__ accel, int s0, int count) {
     using C = typename Storage<S>::C;
-    const int s = blockIdx.x * BLOCK + threadIdx.x;
-    if (s >= g.n) return;
+    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= count) return;
+    const int s = s0 + t;
     int x, y, z;
     site_xyz(s, g, x, y, z);
     const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
@@ -286,15 +288,18 @@ k_init_std(const IN *__restrict__ rho, const IN *__restrict__ u, const IN *__res
 // push to the 19 neighbours.  With a body force a: u = (j + rho a / 2) / rho and the forcing
 // (1 - omega/2) Phi of F = rho a, S = rho (u a + a u); no gradient forcing (no variance).
 // Walls as in the bump scheme (the header).
+// The launch covers sites s0 .. s0 + count - 1 (walls: the interior planes and the wall planes
+// are separate launches, as for k_collide).
 template <int S, bool WALLS = false>
 __global__ void __launch_bounds__(BLOCK)
 k_std(const typename Storage<S>::T *__restrict__ F, typename Storage<S>::T *__restrict__ Fo,
       const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
       StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag,
-      const typename Storage<S>::C *__restrict__ accel) {
+      const typename Storage<S>::C *__restrict__ accel, int s0, int count) {
     using C = typename Storage<S>::C;
-    const int s = blockIdx.x * BLOCK + threadIdx.x;
-    if (s >= g.n) return;
+    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= count) return;
+    const int s = s0 + t;
     int x, y, z;
     site_xyz(s, g, x, y, z);
     const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
