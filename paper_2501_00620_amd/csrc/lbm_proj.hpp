@@ -296,7 +296,14 @@ template <int D> struct ProjTile {
     static constexpr int TX = D == 2 ? PROJ2_TX : 256, TY = D == 2 ? PROJ2_TY : 1, HY = D == 2 ? 1 : 0;
     static constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2 * HY, HN = LX * LY;
     static constexpr int NRING = HN - NT;  // D = 2: two rows of LX and two columns of TY
+    // staged bbar* of the previous step: the source grid plus one more ring
+    static constexpr int BX = LX + 2, BY = LY + 2 * HY, BN = BX * BY;
 };
+
+__device__ __forceinline__ int wrap_mod(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
 
 // LDS slot of ring site r: the top and bottom rows, then the left and right columns (D = 2), or
 // the two ends of the row (D = 1).
@@ -313,27 +320,55 @@ template <int D> __device__ __forceinline__ int proj_ring_slot(int r) {
     }
 }
 
-// Sources of the site held in LDS slot l of the tile at (x0, y0), periodic; false if the slot
-// wraps beyond a lattice smaller than the ring (such slots are never read).
-template <int S, int D, bool TH, bool GATHERED>
+// Sources of the site held in LDS slot l of the tile at (x0, y0), periodic (a lattice smaller
+// than the tile wraps as often as needed).  STAGED: its gather reads the staged bbar* (lb).
+template <int S, int D, bool TH, bool GATHERED, bool STAGED>
 __device__ __forceinline__ bool proj_tile_site(const typename Storage<S>::T *__restrict__ F,
                                                const typename Storage<S>::T *__restrict__ B,
                                                const typename Storage<S>::C *__restrict__ Tf,
                                                typename Storage<S>::C Tconst, const Geo &g,
                                                const StepConst<typename Storage<S>::C> &k, const Codec &cd, int x0,
                                                int y0, int l, typename Storage<S>::C (*lsrc)[ProjTile<D>::HN],
+                                               const void *lbv,
                                                typename Storage<S>::C d[Q], typename Storage<S>::C beta[NB],
                                                PopMoments<typename Storage<S>::C> &m) {
     using C = typename Storage<S>::C;
     using TL = ProjTile<D>;
+    using PS = ProjSet<D>;
+    using PL = ProjLayout<D, TH>;
     const int i = l % TL::LX, j = l / TL::LX;
-    int x = x0 - 1 + i, y = y0 - TL::HY + j;
-    x = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
-    y = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
-    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) return false;
+    const int x = wrap_mod(x0 - 1 + i, g.nx), y = wrap_mod(y0 - TL::HY + j, g.ny);
     const int s = y * g.nx + x;
     const Nbr nb = make_nbr(x, y, 0, g.nx, g.ny, 1);
-    proj_load<S, D, TH, GATHERED>(F, B, (size_t)g.n, nb, s, cd, k.rho_ref, d, beta, m);
+    if constexpr (!STAGED) {
+        proj_load<S, D, TH, GATHERED>(F, B, (size_t)g.n, nb, s, cd, k.rho_ref, d, beta, m);
+    } else {
+        // class sums from HBM, the gather (Eq. 66 over classes) from the staged bbar*
+        const size_t n = g.n;
+        C dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP], acc[PL::NBP], rho = k.rho_ref;
+#pragma unroll
+        for (int c = 0; c < PS::NC; c++) dF[c] = Storage<S>::load(F, (size_t)c * n + s, 0, cd);
+        if constexpr (TH) {
+#pragma unroll
+            for (int c = 0; c < PS::NG; c++) dG[c] = Storage<S>::load(F, (size_t)(PS::NC + c) * n + s, 0, cd);
+        }
+#pragma unroll
+        for (int kk = 0; kk < PL::NBP; kk++) acc[kk] = C(0);
+        const C(*lb)[TL::BN] = (const C(*)[TL::BN])lbv;
+        const int bl = (j + TL::HY) * TL::BX + i + 1;  // this site in the staging grid
+        Unroll<0, PS::NC>::run([&](auto c) {
+            const int up = bl - PS::CY[c] * TL::BX - PS::CX[c];
+            const C wgt = fma(C(class_w<D>(c)), k.rho_ref, dF[c]);
+            rho += dF[c];
+#pragma unroll
+            for (int kk = 0; kk < PL::NBP; kk++) acc[kk] += wgt * lb[kk][up];
+        });
+        const C inv = recip(rho);
+#pragma unroll
+        for (int kk = 0; kk < PL::NBP; kk++) bred[kk] = acc[kk] * inv;
+        proj_expand<D, TH>(dF, dG, bred, d, beta);
+        m = pop_moments(d, k.rho_ref);
+    }
     C o[NSRC];
     predictor_sources(m, beta, site_T(Tf, Tconst, s), k, o);
     lsrc[0][l] = o[0];
@@ -359,19 +394,33 @@ k_proj_fused(const typename Storage<S>::T *__restrict__ F, const typename Storag
     using PL = ProjLayout<D, TH>;
     using TL = ProjTile<D>;
     __shared__ C lsrc[PS::NSP][TL::HN];
+    // D2Q9 stages the previous step's bbar* for the gathers (nine upstream classes); D1Q3, with
+    // three, gathers from L2 directly
+    constexpr bool STAGED = !GATHERED && D == 2;
+    __shared__ C lb[PL::NBP][STAGED ? TL::BN : 1];
     const int x0 = blockIdx.x * TL::TX, y0 = blockIdx.y * TL::TY;
     const size_t n = g.n;
     const int tx = threadIdx.x % TL::TX, ty = threadIdx.x / TL::TX;
+    // phase 0: stage the previous step's bbar* of the source grid plus one ring (periodic)
+    if constexpr (STAGED) {
+        for (int l = threadIdx.x; l < TL::BN; l += TL::NT) {
+            const int x = wrap_mod(x0 - 2 + l % TL::BX, g.nx), y = wrap_mod(y0 - 2 * TL::HY + l / TL::BX, g.ny);
+            const int s = y * g.nx + x;
+#pragma unroll
+            for (int kk = 0; kk < PL::NBP; kk++) lb[kk][l] = Storage<S>::load(B, (size_t)kk * n + s, 0, cd);
+        }
+        __syncthreads();
+    }
     // phase 1: the owned slot (its state stays in registers for phase 2), then the ring
     C d[Q], beta[NB];
     PopMoments<C> m;
-    (void)proj_tile_site<S, D, TH, GATHERED>(F, B, Tf, Tconst, g, k, cd, x0, y0,
-                                             (ty + TL::HY) * TL::LX + tx + 1, lsrc, d, beta, m);
+    (void)proj_tile_site<S, D, TH, GATHERED, STAGED>(F, B, Tf, Tconst, g, k, cd, x0, y0,
+                                                     (ty + TL::HY) * TL::LX + tx + 1, lsrc, lb, d, beta, m);
     for (int r = threadIdx.x; r < TL::NRING; r += TL::NT) {
         C d2[Q], beta2[NB];
         PopMoments<C> m2;
-        (void)proj_tile_site<S, D, TH, GATHERED>(F, B, Tf, Tconst, g, k, cd, x0, y0, proj_ring_slot<D>(r), lsrc, d2,
-                                                 beta2, m2);
+        (void)proj_tile_site<S, D, TH, GATHERED, STAGED>(F, B, Tf, Tconst, g, k, cd, x0, y0, proj_ring_slot<D>(r), lsrc,
+                                                         lb, d2, beta2, m2);
     }
     __syncthreads();
     // phase 2: the owned site
