@@ -177,8 +177,8 @@ int lbm_set_walls(lbm_handle h, int on, const double *u_bottom, const double *u_
  * reallocates the buffers.
  * Supports: modes THERMAL and ISO; storage F64 and F32; lbm_set_fields (the transverse velocity
  * must be 0), lbm_step, lbm_get_moments (transverse u = 0), and lbm_get_state (see
- * lbm_get_projection for its layout).  lbm_set_state, lbm_get_stored, lbm_invariants,
- * lbm_health, walls, body force, a ghost rate and the fused kernel return ARG.
+ * lbm_get_projection for its layout), lbm_health.  lbm_set_state, lbm_get_stored,
+ * lbm_invariants, walls, body force, a ghost rate and the fused kernel return ARG.
  * Errors: ARG (dims, lattice shape, mode, storage, one of those settings), OOM, HIP. */
 int lbm_set_projection(lbm_handle h, int dims);
 
@@ -209,6 +209,11 @@ size_t lbm_lattice_bytes(const lbm_params *p);
 
 /* ---------------------------------------------------------------------------------------------
  * Serving: continuous batching of many independent lattices on one GPU.
+ *
+ * With F32 storage, a one-plane request (nz = 1) without transverse velocity is held as a
+ * projected D2Q9 lattice (lbm_set_projection).  Its result is what that lattice gives stepped
+ * alone with the projection, to the bit; every other request is what the D3Q19 lattice gives
+ * stepped alone with the fused kernel.
  *
  * Requests (each an initial state and a step count) are queued by lbm_server_submit and
  * admitted, first fit in arrival order, whenever their lattice fits the device-memory budget

@@ -999,12 +999,25 @@ int lbm_invariants(lbm_handle h, double out[5]) {
 
 int lbm_health(lbm_handle h, long counts[2], double *max_u) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
-    if (h->proj < 3) return fail(LBM_ERR_ARG, "not available on a projected lattice");
     if (!h->has_state) return fail(LBM_ERR_STATE, "no state");
     const Geo g = geo(h);
     const int rb = red_blocks(h->n);
     double *pmax = h->partial + (size_t)RED_MAX_BLOCKS * RED_K;
-    int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
+    int rc = h->proj < 3 ? dispatch_proj(h, [&](auto SI, auto DI, auto TI) -> int {
+        constexpr int S = decltype(SI)::value, D = decltype(DI)::value;
+        constexpr bool TH = decltype(TI)::value;
+        using TT = typename Storage<S>::T;
+        using C = typename Storage<S>::C;
+        const TT *F = (const TT *)h->F[h->cur];
+        const TT *B = (const TT *)h->B[h->cur];
+        if (h->gathered)
+            hipLaunchKernelGGL((k_proj_health<S, D, TH, true>), dim3(rb), dim3(BLOCK), 0, h->stream, F, B, g, h->codec,
+                               (C)h->p.rho_ref, h->partial, pmax);
+        else
+            hipLaunchKernelGGL((k_proj_health<S, D, TH, false>), dim3(rb), dim3(BLOCK), 0, h->stream, F, B, g, h->codec,
+                               (C)h->p.rho_ref, h->partial, pmax);
+        return check_launch();
+    }) : dispatch_storage(h->p.storage, [&](auto SI) -> int {
         constexpr int S = decltype(SI)::value;
         using TT = typename Storage<S>::T;
         using C = typename Storage<S>::C;

@@ -292,13 +292,15 @@ k_proj_collide(const typename Storage<S>::T *__restrict__ F, const typename Stor
 #ifndef PROJ2_TY
 #define PROJ2_TY 8
 #endif
-template <int D> struct ProjTile {
-    static constexpr int TX = D == 2 ? PROJ2_TX : 256, TY = D == 2 ? PROJ2_TY : 1, HY = D == 2 ? 1 : 0;
+template <int D, int TX_, int TY_> struct ProjTileT {
+    static constexpr int TX = TX_, TY = TY_, HY = D == 2 ? 1 : 0;
     static constexpr int NT = TX * TY, LX = TX + 2, LY = TY + 2 * HY, HN = LX * LY;
     static constexpr int NRING = HN - NT;  // D = 2: two rows of LX and two columns of TY
     // staged bbar* of the previous step: the source grid plus one more ring
     static constexpr int BX = LX + 2, BY = LY + 2 * HY, BN = BX * BY;
 };
+// the one-launch step's tiles (the server uses narrower ones for its small lattices)
+template <int D> using ProjTile = ProjTileT<D, D == 2 ? PROJ2_TX : 256, D == 2 ? PROJ2_TY : 1>;
 
 __device__ __forceinline__ int wrap_mod(int v, int n) {
     v %= n;
@@ -307,8 +309,7 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
 
 // LDS slot of ring site r: the top and bottom rows, then the left and right columns (D = 2), or
 // the two ends of the row (D = 1).
-template <int D> __device__ __forceinline__ int proj_ring_slot(int r) {
-    using TL = ProjTile<D>;
+template <int D, typename TL> __device__ __forceinline__ int proj_ring_slot(int r) {
     if constexpr (D == 1) {
         return r == 0 ? 0 : TL::LX - 1;
     } else {
@@ -321,19 +322,18 @@ template <int D> __device__ __forceinline__ int proj_ring_slot(int r) {
 }
 
 // Sources of the site held in LDS slot l of the tile at (x0, y0), periodic (a lattice smaller
-// than the tile wraps as often as needed).  STAGED: its gather reads the staged bbar* (lb).
-template <int S, int D, bool TH, bool GATHERED, bool STAGED>
-__device__ __forceinline__ bool proj_tile_site(const typename Storage<S>::T *__restrict__ F,
+// than the tile wraps as often as needed), into lsrc (NSP planes of TL::HN).  STAGED: its gather
+// reads the staged bbar* (lb, NBP planes of TL::BN).
+template <int S, int D, bool TH, bool GATHERED, bool STAGED, typename TL>
+__device__ __forceinline__ void proj_tile_site(const typename Storage<S>::T *__restrict__ F,
                                                const typename Storage<S>::T *__restrict__ B,
                                                const typename Storage<S>::C *__restrict__ Tf,
                                                typename Storage<S>::C Tconst, const Geo &g,
                                                const StepConst<typename Storage<S>::C> &k, const Codec &cd, int x0,
-                                               int y0, int l, typename Storage<S>::C (*lsrc)[ProjTile<D>::HN],
-                                               const void *lbv,
-                                               typename Storage<S>::C d[Q], typename Storage<S>::C beta[NB],
-                                               PopMoments<typename Storage<S>::C> &m) {
+                                               int y0, int l, typename Storage<S>::C *lsrc,
+                                               const typename Storage<S>::C *lb, typename Storage<S>::C d[Q],
+                                               typename Storage<S>::C beta[NB], PopMoments<typename Storage<S>::C> &m) {
     using C = typename Storage<S>::C;
-    using TL = ProjTile<D>;
     using PS = ProjSet<D>;
     using PL = ProjLayout<D, TH>;
     const int i = l % TL::LX, j = l / TL::LX;
@@ -354,14 +354,13 @@ __device__ __forceinline__ bool proj_tile_site(const typename Storage<S>::T *__r
         }
 #pragma unroll
         for (int kk = 0; kk < PL::NBP; kk++) acc[kk] = C(0);
-        const C(*lb)[TL::BN] = (const C(*)[TL::BN])lbv;
         const int bl = (j + TL::HY) * TL::BX + i + 1;  // this site in the staging grid
         Unroll<0, PS::NC>::run([&](auto c) {
             const int up = bl - PS::CY[c] * TL::BX - PS::CX[c];
             const C wgt = fma(C(class_w<D>(c)), k.rho_ref, dF[c]);
             rho += dF[c];
 #pragma unroll
-            for (int kk = 0; kk < PL::NBP; kk++) acc[kk] += wgt * lb[kk][up];
+            for (int kk = 0; kk < PL::NBP; kk++) acc[kk] += wgt * lb[kk * TL::BN + up];
         });
         const C inv = recip(rho);
 #pragma unroll
@@ -371,16 +370,115 @@ __device__ __forceinline__ bool proj_tile_site(const typename Storage<S>::T *__r
     }
     C o[NSRC];
     predictor_sources(m, beta, site_T(Tf, Tconst, s), k, o);
-    lsrc[0][l] = o[0];
+    lsrc[l] = o[0];
     if constexpr (D == 2) {
-        lsrc[1][l] = o[1];
-        lsrc[2][l] = o[3];
-        lsrc[3][l] = o[6];
-        lsrc[4][l] = o[7];
+        lsrc[TL::HN + l] = o[1];
+        lsrc[2 * TL::HN + l] = o[3];
+        lsrc[3 * TL::HN + l] = o[6];
+        lsrc[4 * TL::HN + l] = o[7];
     } else {
-        lsrc[1][l] = o[6];
+        lsrc[TL::HN + l] = o[6];
     }
-    return true;
+}
+
+// One step of tile (bx, by) of a projected lattice, by a work-group of TL::NT threads.  Phase 0
+// (D2Q9, scattered state) stages the previous step's bbar* of the source grid plus one ring;
+// phase 1 evaluates the sources of the owned slot (its state stays in registers) and of the ring
+// into LDS; phase 2 takes each owned site's gradient from LDS, collides it and pushes its class
+// sums.  lsrc: NSP x TL::HN, lb: NBP x TL::BN values of LDS (lb unused without staging).  Every
+// thread returns (none leaves early), so a caller may synchronise after it.
+template <int S, int D, bool TH, bool GATHERED, typename TL>
+__device__ __forceinline__ void proj_tile_step(const typename Storage<S>::T *__restrict__ F,
+                                               const typename Storage<S>::T *__restrict__ B,
+                                               typename Storage<S>::T *__restrict__ Fo,
+                                               typename Storage<S>::T *__restrict__ Bo,
+                                               const typename Storage<S>::C *__restrict__ Tf,
+                                               typename Storage<S>::C Tconst, const Geo &g,
+                                               const StepConst<typename Storage<S>::C> &k, const Codec &cd, int bx,
+                                               int by, typename Storage<S>::C *lsrc, typename Storage<S>::C *lb) {
+    using C = typename Storage<S>::C;
+    using PS = ProjSet<D>;
+    using PL = ProjLayout<D, TH>;
+    // D2Q9 stages the previous step's bbar* for the gathers (nine upstream classes); D1Q3, with
+    // three, gathers from L2 directly
+    constexpr bool STAGED = !GATHERED && D == 2;
+    const int x0 = bx * TL::TX, y0 = by * TL::TY;
+    const size_t n = g.n;
+    const int tx = threadIdx.x % TL::TX, ty = threadIdx.x / TL::TX;
+    if constexpr (STAGED) {
+        for (int l = threadIdx.x; l < TL::BN; l += TL::NT) {
+            const int x = wrap_mod(x0 - 2 + l % TL::BX, g.nx), y = wrap_mod(y0 - 2 * TL::HY + l / TL::BX, g.ny);
+            const int s = y * g.nx + x;
+#pragma unroll
+            for (int kk = 0; kk < PL::NBP; kk++) lb[kk * TL::BN + l] = Storage<S>::load(B, (size_t)kk * n + s, 0, cd);
+        }
+        __syncthreads();
+    }
+    C d[Q], beta[NB];
+    PopMoments<C> m;
+    proj_tile_site<S, D, TH, GATHERED, STAGED, TL>(F, B, Tf, Tconst, g, k, cd, x0, y0, (ty + TL::HY) * TL::LX + tx + 1,
+                                                   lsrc, lb, d, beta, m);
+    for (int r = threadIdx.x; r < TL::NRING; r += TL::NT) {
+        C d2[Q], beta2[NB];
+        PopMoments<C> m2;
+        proj_tile_site<S, D, TH, GATHERED, STAGED, TL>(F, B, Tf, Tconst, g, k, cd, x0, y0, proj_ring_slot<D, TL>(r),
+                                                       lsrc, lb, d2, beta2, m2);
+    }
+    __syncthreads();
+    const int x = x0 + tx, y = y0 + ty;
+    if (x < g.nx && y < g.ny) {
+        const int s = y * g.nx + x;
+        const Nbr nb = make_nbr(x, y, 0, g.nx, g.ny, 1);
+        GradAcc<C> acc;
+        grad_init(acc);
+        auto add = [&](auto I) {
+            constexpr int ex = EX[decltype(I)::value], ey = EY[decltype(I)::value];
+            const int l = (ty + TL::HY + ey) * TL::LX + (tx + 1 + ex);
+            C sv[NSRC];
+#pragma unroll
+            for (int c = 0; c < NSRC; c++) sv[c] = C(0);
+            sv[0] = lsrc[l];
+            if constexpr (D == 2) {
+                sv[1] = lsrc[TL::HN + l];
+                sv[3] = lsrc[2 * TL::HN + l];
+                sv[6] = lsrc[3 * TL::HN + l];
+                sv[7] = lsrc[4 * TL::HN + l];
+            } else {
+                sv[6] = lsrc[TL::HN + l];
+            }
+            grad_add<C, decltype(I)::value>(acc, sv, k.K);
+        };
+        C Fv[3], Sv[6];
+        add(std::integral_constant<int, 1>{});
+        add(std::integral_constant<int, 3>{});
+        if constexpr (D == 2) {
+            add(std::integral_constant<int, 2>{});
+            add(std::integral_constant<int, 4>{});
+            add(std::integral_constant<int, 7>{});
+            add(std::integral_constant<int, 8>{});
+            add(std::integral_constant<int, 9>{});
+            add(std::integral_constant<int, 10>{});
+            grad_finish_thin(acc, Fv, Sv);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; c++) Fv[c] = C(0);
+#pragma unroll
+            for (int c = 0; c < 6; c++) Sv[c] = C(0);
+            Fv[0] = -C(0.5) * acc.fF[0];
+            Sv[0] = -acc.fS[0];
+        }
+        collide(d, beta, m, Fv, Sv, site_T(Tf, Tconst, s), k);
+        C dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP];
+        proj_contract<D, TH>(d, beta, dF, dG, bred);
+        unsigned sat = 0;
+        Unroll<0, PS::NC>::run([&](auto c) {
+            const int to = proj_at(nb, PS::CX[c], PS::CY[c]);
+            Storage<S>::store(Fo, (size_t)c * n + to, 0, dF[c], cd, sat);
+            if constexpr (TH && c < PS::NG) Storage<S>::store(Fo, (size_t)(PS::NC + c) * n + to, 0, dG[c], cd, sat);
+        });
+#pragma unroll
+        for (int kk = 0; kk < PL::NBP; kk++) Storage<S>::store(Bo, (size_t)kk * n + s, 0, bred[kk], cd, sat);
+    }
 }
 
 template <int S, int D, bool TH, bool GATHERED>
@@ -390,93 +488,44 @@ k_proj_fused(const typename Storage<S>::T *__restrict__ F, const typename Storag
              const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
              StepConst<typename Storage<S>::C> k, Codec cd) {
     using C = typename Storage<S>::C;
-    using PS = ProjSet<D>;
-    using PL = ProjLayout<D, TH>;
     using TL = ProjTile<D>;
-    __shared__ C lsrc[PS::NSP][TL::HN];
-    // D2Q9 stages the previous step's bbar* for the gathers (nine upstream classes); D1Q3, with
-    // three, gathers from L2 directly
     constexpr bool STAGED = !GATHERED && D == 2;
-    __shared__ C lb[PL::NBP][STAGED ? TL::BN : 1];
-    const int x0 = blockIdx.x * TL::TX, y0 = blockIdx.y * TL::TY;
-    const size_t n = g.n;
-    const int tx = threadIdx.x % TL::TX, ty = threadIdx.x / TL::TX;
-    // phase 0: stage the previous step's bbar* of the source grid plus one ring (periodic)
-    if constexpr (STAGED) {
-        for (int l = threadIdx.x; l < TL::BN; l += TL::NT) {
-            const int x = wrap_mod(x0 - 2 + l % TL::BX, g.nx), y = wrap_mod(y0 - 2 * TL::HY + l / TL::BX, g.ny);
-            const int s = y * g.nx + x;
+    __shared__ C lsrc[ProjSet<D>::NSP * TL::HN];
+    __shared__ C lb[STAGED ? ProjLayout<D, TH>::NBP * TL::BN : 1];
+    proj_tile_step<S, D, TH, GATHERED, TL>(F, B, Fo, Bo, Tf, Tconst, g, k, cd, blockIdx.x, blockIdx.y, lsrc, lb);
+}
+
+// ---- health of a projected lattice: non-finite sites, rho <= 0 sites, max |u*| -----------------
+template <int S, int D, bool TH, bool GATHERED>
+__global__ void __launch_bounds__(BLOCK)
+k_proj_health(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B, Geo g,
+              Codec cd, typename Storage<S>::C rho_ref, double *__restrict__ partial_sum,
+              double *__restrict__ partial_max) {
+    using C = typename Storage<S>::C;
+    double cnt[2] = {0, 0};
+    double mx[1] = {0};
+    for (int s = blockIdx.x * BLOCK + threadIdx.x; s < g.n; s += gridDim.x * BLOCK) {
+        int x, y, z;
+        site_xyz(s, g, x, y, z);
+        const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
+        C d[Q], beta[NB];
+        PopMoments<C> m;
+        proj_load<S, D, TH, GATHERED>(F, B, (size_t)g.n, nb, s, cd, rho_ref, d, beta, m);
+        bool finite = true;
 #pragma unroll
-            for (int kk = 0; kk < PL::NBP; kk++) lb[kk][l] = Storage<S>::load(B, (size_t)kk * n + s, 0, cd);
+        for (int i = 0; i < Q; i++) finite = finite && isfinite((double)d[i]);
+#pragma unroll
+        for (int c = 0; c < NB; c++) finite = finite && isfinite((double)beta[c]);
+        if (!finite) cnt[0] += 1.0;
+        if (!(m.rho > C(0))) cnt[1] += 1.0;
+        if (finite && m.rho > C(0)) {
+            const double ux = (double)m.jx / (double)m.rho, uy = (double)m.jy / (double)m.rho;
+            mx[0] = fmax(mx[0], sqrt(ux * ux + uy * uy));
         }
-        __syncthreads();
     }
-    // phase 1: the owned slot (its state stays in registers for phase 2), then the ring
-    C d[Q], beta[NB];
-    PopMoments<C> m;
-    (void)proj_tile_site<S, D, TH, GATHERED, STAGED>(F, B, Tf, Tconst, g, k, cd, x0, y0,
-                                                     (ty + TL::HY) * TL::LX + tx + 1, lsrc, lb, d, beta, m);
-    for (int r = threadIdx.x; r < TL::NRING; r += TL::NT) {
-        C d2[Q], beta2[NB];
-        PopMoments<C> m2;
-        (void)proj_tile_site<S, D, TH, GATHERED, STAGED>(F, B, Tf, Tconst, g, k, cd, x0, y0, proj_ring_slot<D>(r), lsrc,
-                                                         lb, d2, beta2, m2);
-    }
+    block_reduce_store<2, false>(cnt, partial_sum);
     __syncthreads();
-    // phase 2: the owned site
-    const int x = x0 + tx, y = y0 + ty;
-    if (x >= g.nx || y >= g.ny) return;
-    const int s = y * g.nx + x;
-    const Nbr nb = make_nbr(x, y, 0, g.nx, g.ny, 1);
-    GradAcc<C> acc;
-    grad_init(acc);
-    auto add = [&](auto I) {
-        constexpr int ex = EX[decltype(I)::value], ey = EY[decltype(I)::value];
-        const int l = (ty + TL::HY + ey) * TL::LX + (tx + 1 + ex);
-        C sv[NSRC];
-#pragma unroll
-        for (int c = 0; c < NSRC; c++) sv[c] = C(0);
-        sv[0] = lsrc[0][l];
-        if constexpr (D == 2) {
-            sv[1] = lsrc[1][l];
-            sv[3] = lsrc[2][l];
-            sv[6] = lsrc[3][l];
-            sv[7] = lsrc[4][l];
-        } else {
-            sv[6] = lsrc[1][l];
-        }
-        grad_add<C, decltype(I)::value>(acc, sv, k.K);
-    };
-    C Fv[3], Sv[6];
-    add(std::integral_constant<int, 1>{});
-    add(std::integral_constant<int, 3>{});
-    if constexpr (D == 2) {
-        add(std::integral_constant<int, 2>{});
-        add(std::integral_constant<int, 4>{});
-        add(std::integral_constant<int, 7>{});
-        add(std::integral_constant<int, 8>{});
-        add(std::integral_constant<int, 9>{});
-        add(std::integral_constant<int, 10>{});
-        grad_finish_thin(acc, Fv, Sv);
-    } else {
-#pragma unroll
-        for (int c = 0; c < 3; c++) Fv[c] = C(0);
-#pragma unroll
-        for (int c = 0; c < 6; c++) Sv[c] = C(0);
-        Fv[0] = -C(0.5) * acc.fF[0];
-        Sv[0] = -acc.fS[0];
-    }
-    collide(d, beta, m, Fv, Sv, site_T(Tf, Tconst, s), k);
-    C dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP];
-    proj_contract<D, TH>(d, beta, dF, dG, bred);
-    unsigned sat = 0;
-    Unroll<0, PS::NC>::run([&](auto c) {
-        const int to = proj_at(nb, PS::CX[c], PS::CY[c]);
-        Storage<S>::store(Fo, (size_t)c * n + to, 0, dF[c], cd, sat);
-        if constexpr (TH && c < PS::NG) Storage<S>::store(Fo, (size_t)(PS::NC + c) * n + to, 0, dG[c], cd, sat);
-    });
-#pragma unroll
-    for (int kk = 0; kk < PL::NBP; kk++) Storage<S>::store(Bo, (size_t)kk * n + s, 0, bred[kk], cd, sat);
+    block_reduce_store<1, true>(mx, partial_max);
 }
 
 // ---- readout of corrected moments (after k_proj_predict on the same state) ----------------------

@@ -12,6 +12,11 @@
 // lbm_step at admission), replays the bundle graph over all resident lattices, retires those
 // whose steps are done (health check, moments to host, memory freed), and timestamps each
 // request.  Requests submitted while a bundle runs wait at most one bundle for admission.
+//
+// With FP32 storage, a one-plane request without transverse velocity is served as a projected
+// D2Q9 lattice (lbm_set_projection): the same step on 18 (THERMAL) or 12 (ISO) values per site
+// instead of 25, swept by k_serve_proj.  Its result is what the same lattice stepped alone with
+// that projection gives, to the bit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,6 +33,7 @@
 #include "../../include/lbm.h"
 #include "lbm_fused.hpp"
 #include "lbm_internal.hpp"
+#include "lbm_proj.hpp"
 
 using namespace lbm;
 
@@ -45,6 +51,7 @@ struct ServeDesc {
     StepConst<float> k;
     unsigned *flag;  // the lattice's own range flag
     Codec cd;
+    int proj;        // 1: a projected D2Q9 lattice (k_serve_proj)
 };
 
 struct TileRef {
@@ -85,6 +92,33 @@ k_serve(const ServeDesc *__restrict__ descs, const TileRef *__restrict__ tiles, 
     }
 }
 
+// Projected D2Q9 lattices (FP32): tiles [ntiles[1], ntiles[2]) of the table.  The per-tile step
+// and the tiles are those of the one-launch kernel of a lattice stepped alone, so the results
+// agree to the bit: which sites of a tile are ring sites decides how the compiler may fuse their
+// source arithmetic, so another tile shape would change the last bit.
+using ProjServeTile = ProjTile<2>;
+__global__ void __launch_bounds__(ProjServeTile::NT)
+k_serve_proj(const ServeDesc *__restrict__ descs, const TileRef *__restrict__ tiles, const int *__restrict__ ntiles,
+             int step) {
+    using TL = ProjServeTile;
+    __shared__ float lsrc[ProjSet<2>::NSP * TL::HN];
+    __shared__ float lb[ProjLayout<2, true>::NBP * TL::BN];
+    for (int t = ntiles[1] + (int)blockIdx.x; t < ntiles[2]; t += (int)gridDim.x) {
+        const TileRef e = tiles[t];
+        const ServeDesc &d = descs[e.lat];
+        if (step >= d.steps_left) continue;  // this lattice is done for the bundle (uniform)
+        const int cur = (d.cur0 + step) & 1;
+        const int bx = e.tile % d.fg.tiles_x, by = e.tile / d.fg.tiles_x;
+        const float *F = (const float *)d.F[cur], *B = (const float *)d.B[cur];
+        float *Fo = (float *)d.F[1 - cur], *Bo = (float *)d.B[1 - cur];
+        if (d.k.iso)
+            proj_tile_step<1, 2, false, false, TL>(F, B, Fo, Bo, d.Tf, d.Tconst, d.g, d.k, d.cd, bx, by, lsrc, lb);
+        else
+            proj_tile_step<1, 2, true, false, TL>(F, B, Fo, Bo, d.Tf, d.Tconst, d.g, d.k, d.cd, bx, by, lsrc, lb);
+        __syncthreads();  // the next tile reuses the LDS
+    }
+}
+
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -111,6 +145,7 @@ struct lbm_server {
     int device = 0;
     int grid = 0;       // persistent work-groups of the general kernel
     int grid_thin = 0;  // persistent work-groups of the one-plane kernel
+    int grid_proj = 0;  // persistent work-groups of the projected kernel
 
     std::mutex mu;
     std::condition_variable cv;       // worker wake-up
@@ -131,8 +166,8 @@ struct lbm_server {
     std::vector<ServeDesc> h_desc;
     std::vector<TileRef> h_tiles;
     bool tables_dirty = true;
-    int n_thin = 0, n_all = 0;                // tile counts of the current table
-    bool graph_thin = false, graph_gen = false;  // kernels the captured bundle launches
+    int n_thin = 0, n_all = 0, n_proj_end = 0;   // tile counts of the current table
+    bool graph_thin = false, graph_gen = false, graph_proj = false;  // kernels the bundle launches
     hipGraphExec_t graph = nullptr;
 
     // counters
@@ -159,6 +194,16 @@ void fail_request(lbm_server *s, Request &r, const std::string &msg) {
     r.u.clear();
     r.T.clear();
     s->n_failed++;
+}
+
+// A request is served as a projected D2Q9 lattice when the storage is FP32 and the lattice is
+// one plane with no transverse velocity.
+bool serve_projected(const lbm_server *s, const Request &r) {
+    if (s->prm.storage != LBM_F32 || r.p.nz != 1 || r.p.mode == LBM_STANDARD) return false;
+    const size_t n = (size_t)r.p.nx * r.p.ny;
+    for (size_t i = 0; i < n; i++)
+        if (r.u[2 * n + i] != 0.0) return false;
+    return true;
 }
 
 // Admit queued requests that fit (first fit, arrival order).  Called by the worker, unlocked
@@ -191,9 +236,11 @@ void admit(lbm_server *s) {
         lbm_params p = r->p;
         p.storage = s->prm.storage;
         lbm_handle h = nullptr;
+        const bool proj = serve_projected(s, *r);
         int rc = lbm_create(&p, s->stream, &h);
+        if (!rc && proj) rc = lbm_set_projection(h, 2);
         if (!rc) rc = lbm_set_fields(h, r->rho.data(), r->u.data(), r->T.data(), LBM_DTYPE_F64, 0);
-        if (!rc) rc = lbm_set_kernel(h, 2);
+        if (!rc && !proj) rc = lbm_set_kernel(h, 2);
         if (!rc) rc = lbm_step(h, 1);  // from the gathered initial state
         std::string err = rc ? lbm_last_error() : "";
         std::lock_guard<std::mutex> lk(s->mu);
@@ -233,12 +280,18 @@ int upload_tables(lbm_server *s) {
         d.cur0 = h->cur;
         d.steps_left = (int)std::min<long>(r.steps_left, s->prm.bundle_steps);
         d.g = Geo{h->p.nx, h->p.ny, h->p.nz, h->n};
-        dispatch_serve(s->prm.storage, [&](auto SI) -> int {
-            constexpr int S = decltype(SI)::value;
-            d.fg = d.g.nz == 1 ? fused_geometry_t<ServeTile<S, true>>(d.g, s->grid_thin)
-                               : fused_geometry_t<ServeTile<S, false>>(d.g, s->grid);
-            return 0;
-        });
+        d.proj = h->proj < 3 ? 1 : 0;
+        if (d.proj) {
+            d.fg = FusedGeo{(h->p.nx + ProjServeTile::TX - 1) / ProjServeTile::TX,
+                            (h->p.ny + ProjServeTile::TY - 1) / ProjServeTile::TY, 1, 1};
+        } else {
+            dispatch_serve(s->prm.storage, [&](auto SI) -> int {
+                constexpr int S = decltype(SI)::value;
+                d.fg = d.g.nz == 1 ? fused_geometry_t<ServeTile<S, true>>(d.g, s->grid_thin)
+                                   : fused_geometry_t<ServeTile<S, false>>(d.g, s->grid);
+                return 0;
+            });
+        }
         const double omega = 1.0 / (h->p.tau + 0.5);
         d.k.omega = (float)omega;
         d.k.half_omega = (float)(0.5 * omega);
@@ -253,18 +306,21 @@ int upload_tables(lbm_server *s) {
         s->h_desc.push_back(d);
     }
     if (s->tables_dirty) {
-        // tiles of one-plane lattices first (the one-plane kernel), then the others
-        for (int pass = 0; pass < 2; pass++) {
+        // tiles of one-plane lattices first (the one-plane kernel), then the other D3Q19 ones,
+        // then the projected ones
+        for (int pass = 0; pass < 3; pass++) {
             for (size_t a = 0; a < s->h_desc.size(); a++) {
                 const ServeDesc &d = s->h_desc[a];
-                if ((d.g.nz == 1) != (pass == 0)) continue;
+                const int kind = d.proj ? 2 : (d.g.nz == 1 ? 0 : 1);
+                if (kind != pass) continue;
                 const int nt = d.fg.tiles_x * d.fg.tiles_y * d.fg.nchunks;
                 for (int t = 0; t < nt; t++) s->h_tiles.push_back(TileRef{(int)a, t});
             }
             if (pass == 0) s->n_thin = (int)s->h_tiles.size();
+            if (pass == 1) s->n_all = (int)s->h_tiles.size();
         }
-        s->n_all = (int)s->h_tiles.size();
-        const int nt = s->n_all;
+        s->n_proj_end = (int)s->h_tiles.size();
+        const int nt = s->n_proj_end;
         if (nt > s->tile_cap) {
             if (s->graph) {
                 (void)hipGraphExecDestroy(s->graph);
@@ -276,14 +332,14 @@ int upload_tables(lbm_server *s) {
         }
         if (nt && hipMemcpyAsync(s->d_tiles, s->h_tiles.data(), sizeof(TileRef) * nt, hipMemcpyHostToDevice, s->stream) != hipSuccess)
             return LBM_ERR_HIP;
-        const int counts[2] = {s->n_thin, s->n_all};
+        const int counts[3] = {s->n_thin, s->n_all, s->n_proj_end};
         if (hipMemcpyAsync(s->d_ntiles, counts, sizeof(counts), hipMemcpyHostToDevice, s->stream) != hipSuccess)
             return LBM_ERR_HIP;
         // the copy reads a stack array: make it complete before it goes out of scope
         if (hipStreamSynchronize(s->stream) != hipSuccess) return LBM_ERR_HIP;
         // a bundle launches only the kernels with tiles to sweep
-        const bool want_thin = s->n_thin > 0, want_gen = s->n_all > s->n_thin;
-        if (s->graph && (want_thin != s->graph_thin || want_gen != s->graph_gen)) {
+        const bool want_thin = s->n_thin > 0, want_gen = s->n_all > s->n_thin, want_proj = s->n_proj_end > s->n_all;
+        if (s->graph && (want_thin != s->graph_thin || want_gen != s->graph_gen || want_proj != s->graph_proj)) {
             (void)hipGraphExecDestroy(s->graph);
             s->graph = nullptr;
         }
@@ -299,7 +355,7 @@ int upload_tables(lbm_server *s) {
 int capture_graph(lbm_server *s) {
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_ERR_HIP;
-    const bool thin = s->n_thin > 0, gen = s->n_all > s->n_thin;
+    const bool thin = s->n_thin > 0, gen = s->n_all > s->n_thin, proj = s->n_proj_end > s->n_all;
     int rc = dispatch_serve(s->prm.storage, [&](auto SI) -> int {
         constexpr int S = decltype(SI)::value;
         for (int st = 0; st < s->prm.bundle_steps; st++) {
@@ -309,11 +365,15 @@ int capture_graph(lbm_server *s) {
             if (gen)
                 hipLaunchKernelGGL((k_serve<S, false>), dim3(s->grid), dim3(ServeTile<S, false>::NT), 0, s->stream, s->d_desc,
                                    s->d_tiles, s->d_ntiles, st);
+            if (proj)
+                hipLaunchKernelGGL(k_serve_proj, dim3(s->grid_proj), dim3(ProjServeTile::NT), 0, s->stream, s->d_desc,
+                                   s->d_tiles, s->d_ntiles, st);
         }
         return LBM_OK;
     });
     s->graph_thin = thin;
     s->graph_gen = gen;
+    s->graph_proj = proj;
     hipError_t e = hipStreamEndCapture(s->stream, &g);
     if (rc || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -476,6 +536,10 @@ int lbm_server_create(const lbm_server_params *p, void *hip_stream, lbm_server_h
         return 0;
     });
     s->grid_thin = cus * (per_cu > 0 ? per_cu : 1);
+    int per_cu_proj = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_proj, k_serve_proj, ProjServeTile::NT, 0) != hipSuccess)
+        per_cu_proj = 1;
+    s->grid_proj = cus * (per_cu_proj > 0 ? per_cu_proj : 1);
     if (hip_stream) {
         s->stream = (hipStream_t)hip_stream;
     } else {
@@ -486,8 +550,8 @@ int lbm_server_create(const lbm_server_params *p, void *hip_stream, lbm_server_h
         s->own_stream = true;
     }
     hipError_t e = hipMalloc(&s->d_desc, sizeof(ServeDesc) * p->max_lattices);
-    if (e == hipSuccess) e = hipMalloc(&s->d_ntiles, 2 * sizeof(int));
-    if (e == hipSuccess) e = hipMemset(s->d_ntiles, 0, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&s->d_ntiles, 3 * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(s->d_ntiles, 0, 3 * sizeof(int));
     if (e != hipSuccess) {
         lbm_server_destroy(s);
         return set_error(LBM_ERR_OOM, "server tables");

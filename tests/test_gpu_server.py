@@ -28,7 +28,13 @@ def alone(fields, tau, steps, storage, mode="thermal"):
     rho, u, T = fields
     nz, ny, nx = rho.shape
     rho_ref, T_ref = lbm().codec_reference(rho, T)  # the server's default reference
-    g = lbm().Lattice(nx, ny, nz, tau, storage=storage, mode=mode, kernel="fused", rho_ref=rho_ref, T_ref=T_ref)
+    # the server holds an FP32 one-plane lattice without transverse velocity as a projected D2Q9
+    # lattice; alone, the same projection steps it
+    projected = storage == "f32" and nz == 1 and not np.any(np.asarray(u)[2])
+    g = lbm().Lattice(nx, ny, nz, tau, storage=storage, mode=mode, kernel="auto" if projected else "fused",
+                      rho_ref=rho_ref, T_ref=T_ref)
+    if projected:
+        g.set_projection(2)
     g.set_fields(rho, u, T)
     g.step(steps)
     r, uu, TT = g.moments()
@@ -117,3 +123,22 @@ def test_iso_mode_and_single_step_requests():
             np.testing.assert_array_equal(a, b)
         for a, b in zip(srv.fetch(r2), alone((rho, u, T), 0.7, 23, "f32", mode="iso")):
             np.testing.assert_array_equal(a, b)
+
+
+def test_projected_and_d3q19_one_plane_requests_side_by_side():
+    # FP32 one-plane requests without transverse velocity are served projected (THERMAL and ISO);
+    # one with a transverse velocity stays D3Q19.  Each equals its alone run to the bit.
+    L = lbm()
+    a = wl.riemann2d_request(np.random.default_rng(11), n=96)
+    rho, u, T = wl.fourier_fields(70, 45, 1, seed=12, u_max=0.15)
+    flat = (rho, np.concatenate([u[:2], np.zeros_like(u[2:])]), T)
+    with L.Server(budget_bytes=1 << 30, bundle_steps=9, storage="f32") as srv:
+        r1 = srv.submit(*a, tau=0.8, steps=50)
+        r2 = srv.submit(*flat, tau=0.7, steps=41, mode="iso")
+        r3 = srv.submit(rho, u, T, tau=0.7, steps=33)  # u_z != 0: D3Q19
+        for r in (r1, r2, r3):
+            assert srv.wait(r) == "done", srv.error(r)
+        for rid, ref in ((r1, alone(a, 0.8, 50, "f32")), (r2, alone(flat, 0.7, 41, "f32", mode="iso")),
+                         (r3, alone((rho, u, T), 0.7, 33, "f32"))):
+            for x, y in zip(srv.fetch(rid), ref):
+                np.testing.assert_array_equal(x, y)
