@@ -131,15 +131,16 @@ template <typename Fn> int dispatch_storage(int storage, Fn &&fn) {
     return fail(LBM_ERR_ARG, "unknown storage %d", storage);
 }
 
-// Projected lattices (lbm_set_projection): F64 / F32 storage, D = 2 or 1, energy-conserving or not.
+// Projected lattices (lbm_set_projection): F64, F32 or BF16 storage (BF16 codes hold the deviation
+// itself: no per-field scale), D = 2 or 1, energy-conserving or not.
 template <typename Fn> int dispatch_proj(const lbm_lattice *h, Fn &&fn) {
     using D2 = std::integral_constant<int, 2>;
     using D1 = std::integral_constant<int, 1>;
     const bool th = h->p.mode == LBM_THERMAL;
     return dispatch_storage(h->p.storage, [&](auto SI) -> int {
         constexpr int S = decltype(SI)::value;
-        if constexpr (S > 1) {
-            return fail(LBM_ERR_ARG, "projected lattices store F64 or F32");
+        if constexpr (S == 2) {
+            return fail(LBM_ERR_ARG, "projected lattices store F64, F32 or BF16");
         } else {
             if (h->proj == 2)
                 return th ? fn(SI, D2{}, std::true_type{}) : fn(SI, D2{}, std::false_type{});
@@ -264,22 +265,22 @@ int step_proj(lbm_lattice *h) {
             T *Bo = (T *)h->B[1 - h->cur];
             if (h->gathered)
                 hipLaunchKernelGGL((k_proj_fused<S, D, TH, true>), tiles, dim3(TL::NT), 0, h->stream, F, B, Fo, Bo,
-                                   (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
+                                   (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->flag);
             else
                 hipLaunchKernelGGL((k_proj_fused<S, D, TH, false>), tiles, dim3(TL::NT), 0, h->stream, F, B, Fo, Bo,
-                                   (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
+                                   (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->flag);
         } else if (h->gathered) {
             hipLaunchKernelGGL((k_proj_predict<S, D, TH, true>), grid, block, 0, h->stream, F, B, (C *)h->src,
                                (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
             hipLaunchKernelGGL((k_proj_collide<S, D, TH, true>), grid, block, 0, h->stream, F, B, (const C *)h->src,
                                (T *)h->F[1 - h->cur], (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k,
-                               h->codec);
+                               h->codec, h->flag);
         } else {
             hipLaunchKernelGGL((k_proj_predict<S, D, TH, false>), grid, block, 0, h->stream, F, B, (C *)h->src,
                                (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
             hipLaunchKernelGGL((k_proj_collide<S, D, TH, false>), grid, block, 0, h->stream, F, B, (const C *)h->src,
                                (T *)h->F[1 - h->cur], (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k,
-                               h->codec);
+                               h->codec, h->flag);
         }
         int rc = check_launch();
         if (rc) return rc;
@@ -444,8 +445,8 @@ int lbm_set_projection(lbm_handle h, int dims) {
     if (dims == 1 && (h->p.ny != 1 || h->p.nz != 1)) return fail(LBM_ERR_ARG, "a D1Q3 projection needs ny = nz = 1");
     if (dims < 3) {
         if (h->p.mode == LBM_STANDARD) return fail(LBM_ERR_ARG, "the standard comparator is not projected");
-        if (h->p.storage != LBM_F64 && h->p.storage != LBM_F32)
-            return fail(LBM_ERR_ARG, "projected lattices store F64 or F32");
+        if (h->p.storage == LBM_F16DEV)
+            return fail(LBM_ERR_ARG, "projected lattices store F64, F32 or BF16 (FP16 codes need per-field scales)");
         if (h->kernel == 2) return fail(LBM_ERR_ARG, "projected lattices step with their own two-pass kernels");
         if (h->walls || h->accel || h->tau_ghost > 0.0)
             return fail(LBM_ERR_ARG, "projected lattices have no walls, body force or ghost rate");
@@ -683,7 +684,7 @@ int lbm_set_fields(lbm_handle h, const void *rho, const void *u, const void *T, 
     if (!rc) rc = read_clear_flag(h, &sat);
     if (stage) (void)hipFree(stage);
     if (rc) return rc;
-    if (h->proj < 3 && sat) return fail(LBM_ERR_ARG, "a projected lattice takes no transverse velocity");
+    if (h->proj < 3 && (sat & 2u)) return fail(LBM_ERR_ARG, "a projected lattice takes no transverse velocity");
     h->cur = 0;
     h->gathered = true;
     h->has_state = true;

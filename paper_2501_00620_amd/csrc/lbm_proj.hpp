@@ -20,7 +20,8 @@
 // nine in-plane offsets for D = 2, the two x offsets for D = 1), which is what the D3Q19 stencil
 // reduces to when the transverse neighbours are the site's own column.
 //
-// Stored per site (deviations from the references, storage F64 or F32):
+// Stored per site (deviations from the references; storage F64, F32, or BF16 deviation codes,
+// which hold the deviation itself and so need no per-field scale):
 //   F planes: dF_c for the NC classes, then dG_c for the NG classes with transverse members
 //             (energy-conserving mode only)
 //   B planes: the in-plane bbar deviations (D = 2: xx yy xy; D = 1: xx), then the transverse trace
@@ -47,6 +48,33 @@ template <> struct ProjSet<1> {
     static constexpr int CX[NC] = {0, 1, -1};
     static constexpr int CY[NC] = {0, 0, 0};
 };
+
+// Loads and stores of the projected state.  BF16 codes hold the deviation itself (their scale is
+// always 1), so no codec is read: in the server the codec sits in a descriptor in device memory,
+// and a scale multiply per access would reload it around every store.
+template <int S> __device__ __forceinline__ typename Storage<S>::C proj_ld(const typename Storage<S>::T *p, size_t i) {
+    static_assert(S != 2, "FP16 codes need per-field scales");
+    if constexpr (S == 3)
+        return bf16_bits_to_float(p[i]);
+    else
+        return p[i];
+}
+template <int S>
+__device__ __forceinline__ void proj_st(typename Storage<S>::T *p, size_t i, typename Storage<S>::C v, unsigned &sat) {
+    static_assert(S != 2, "FP16 codes need per-field scales");
+    if constexpr (S == 3)
+        p[i] = float_to_bf16_bits(v, sat);
+    else
+        p[i] = v;
+}
+
+// A 16-bit code overflowed somewhere in this wavefront: one lane records it.  (A diverging
+// lattice overflows at every site and every step until its health check retires it; one store
+// per wavefront instead of one atomic per site keeps that from serialising the sweep.)
+__device__ __forceinline__ void proj_flag_overflow(unsigned *flag, unsigned sat) {
+    const unsigned long long m = __ballot(sat != 0u);
+    if (m && __lane_id() == (unsigned)(__ffsll((long long)m) - 1)) *flag = 1u;
+}
 
 // |e_i,t|^2, the squared transverse speed of population i
 template <int D> constexpr int et2(int i) { return D == 2 ? EZ[i] * EZ[i] : EY[i] * EY[i] + EZ[i] * EZ[i]; }
@@ -147,14 +175,14 @@ __device__ __forceinline__ void proj_load(const typename Storage<S>::T *__restri
     using PL = ProjLayout<D, TH>;
     C dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP];
 #pragma unroll
-    for (int c = 0; c < PS::NC; c++) dF[c] = Storage<S>::load(F, (size_t)c * n + s, 0, cd);
+    for (int c = 0; c < PS::NC; c++) dF[c] = proj_ld<S>(F, (size_t)c * n + s);
     if constexpr (TH) {
 #pragma unroll
-        for (int c = 0; c < PS::NG; c++) dG[c] = Storage<S>::load(F, (size_t)(PS::NC + c) * n + s, 0, cd);
+        for (int c = 0; c < PS::NG; c++) dG[c] = proj_ld<S>(F, (size_t)(PS::NC + c) * n + s);
     }
     if constexpr (GATHERED) {
 #pragma unroll
-        for (int k = 0; k < PL::NBP; k++) bred[k] = Storage<S>::load(B, (size_t)k * n + s, 0, cd);
+        for (int k = 0; k < PL::NBP; k++) bred[k] = proj_ld<S>(B, (size_t)k * n + s);
     } else {
         C acc[PL::NBP], rho = rho_ref;
 #pragma unroll
@@ -164,7 +192,7 @@ __device__ __forceinline__ void proj_load(const typename Storage<S>::T *__restri
             const C wgt = fma(C(class_w<D>(c)), rho_ref, dF[c]);
             rho += dF[c];
 #pragma unroll
-            for (int k = 0; k < PL::NBP; k++) acc[k] += wgt * Storage<S>::load(B, (size_t)k * n + up, 0, cd);
+            for (int k = 0; k < PL::NBP; k++) acc[k] += wgt * proj_ld<S>(B, (size_t)k * n + up);
         });
         const C inv = recip(rho);
 #pragma unroll
@@ -253,7 +281,8 @@ __global__ void __launch_bounds__(BLOCK)
 k_proj_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
                const typename Storage<S>::C *__restrict__ src, typename Storage<S>::T *__restrict__ Fo,
                typename Storage<S>::T *__restrict__ Bo, const typename Storage<S>::C *__restrict__ Tf,
-               typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd) {
+               typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd,
+               unsigned *__restrict__ flag) {
     using C = typename Storage<S>::C;
     using PS = ProjSet<D>;
     using PL = ProjLayout<D, TH>;
@@ -273,11 +302,12 @@ k_proj_collide(const typename Storage<S>::T *__restrict__ F, const typename Stor
     unsigned sat = 0;
     Unroll<0, PS::NC>::run([&](auto c) {
         const int to = proj_at(nb, PS::CX[c], PS::CY[c]);
-        Storage<S>::store(Fo, (size_t)c * g.n + to, 0, dF[c], cd, sat);
-        if constexpr (TH && c < PS::NG) Storage<S>::store(Fo, (size_t)(PS::NC + c) * g.n + to, 0, dG[c], cd, sat);
+        proj_st<S>(Fo, (size_t)c * g.n + to, dF[c], sat);
+        if constexpr (TH && c < PS::NG) proj_st<S>(Fo, (size_t)(PS::NC + c) * g.n + to, dG[c], sat);
     });
 #pragma unroll
-    for (int kk = 0; kk < PL::NBP; kk++) Storage<S>::store(Bo, (size_t)kk * g.n + s, 0, bred[kk], cd, sat);
+    for (int kk = 0; kk < PL::NBP; kk++) proj_st<S>(Bo, (size_t)kk * g.n + s, bred[kk], sat);
+    if constexpr (S == 3) proj_flag_overflow(flag, sat);
 }
 
 // ---- one-launch step: sources of a tile and its one-site halo in LDS -------------------------------
@@ -347,10 +377,10 @@ __device__ __forceinline__ void proj_tile_site(const typename Storage<S>::T *__r
         const size_t n = g.n;
         C dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP], acc[PL::NBP], rho = k.rho_ref;
 #pragma unroll
-        for (int c = 0; c < PS::NC; c++) dF[c] = Storage<S>::load(F, (size_t)c * n + s, 0, cd);
+        for (int c = 0; c < PS::NC; c++) dF[c] = proj_ld<S>(F, (size_t)c * n + s);
         if constexpr (TH) {
 #pragma unroll
-            for (int c = 0; c < PS::NG; c++) dG[c] = Storage<S>::load(F, (size_t)(PS::NC + c) * n + s, 0, cd);
+            for (int c = 0; c < PS::NG; c++) dG[c] = proj_ld<S>(F, (size_t)(PS::NC + c) * n + s);
         }
 #pragma unroll
         for (int kk = 0; kk < PL::NBP; kk++) acc[kk] = C(0);
@@ -395,7 +425,8 @@ __device__ __forceinline__ void proj_tile_step(const typename Storage<S>::T *__r
                                                const typename Storage<S>::C *__restrict__ Tf,
                                                typename Storage<S>::C Tconst, const Geo &g,
                                                const StepConst<typename Storage<S>::C> &k, const Codec &cd, int bx,
-                                               int by, typename Storage<S>::C *lsrc, typename Storage<S>::C *lb) {
+                                               int by, typename Storage<S>::C *lsrc, typename Storage<S>::C *lb,
+                                               unsigned *__restrict__ flag) {
     using C = typename Storage<S>::C;
     using PS = ProjSet<D>;
     using PL = ProjLayout<D, TH>;
@@ -410,7 +441,7 @@ __device__ __forceinline__ void proj_tile_step(const typename Storage<S>::T *__r
             const int x = wrap_mod(x0 - 2 + l % TL::BX, g.nx), y = wrap_mod(y0 - 2 * TL::HY + l / TL::BX, g.ny);
             const int s = y * g.nx + x;
 #pragma unroll
-            for (int kk = 0; kk < PL::NBP; kk++) lb[kk * TL::BN + l] = Storage<S>::load(B, (size_t)kk * n + s, 0, cd);
+            for (int kk = 0; kk < PL::NBP; kk++) lb[kk * TL::BN + l] = proj_ld<S>(B, (size_t)kk * n + s);
         }
         __syncthreads();
     }
@@ -473,11 +504,12 @@ __device__ __forceinline__ void proj_tile_step(const typename Storage<S>::T *__r
         unsigned sat = 0;
         Unroll<0, PS::NC>::run([&](auto c) {
             const int to = proj_at(nb, PS::CX[c], PS::CY[c]);
-            Storage<S>::store(Fo, (size_t)c * n + to, 0, dF[c], cd, sat);
-            if constexpr (TH && c < PS::NG) Storage<S>::store(Fo, (size_t)(PS::NC + c) * n + to, 0, dG[c], cd, sat);
+            proj_st<S>(Fo, (size_t)c * n + to, dF[c], sat);
+            if constexpr (TH && c < PS::NG) proj_st<S>(Fo, (size_t)(PS::NC + c) * n + to, dG[c], sat);
         });
 #pragma unroll
-        for (int kk = 0; kk < PL::NBP; kk++) Storage<S>::store(Bo, (size_t)kk * n + s, 0, bred[kk], cd, sat);
+        for (int kk = 0; kk < PL::NBP; kk++) proj_st<S>(Bo, (size_t)kk * n + s, bred[kk], sat);
+        if constexpr (S == 3) proj_flag_overflow(flag, sat);
     }
 }
 
@@ -486,13 +518,13 @@ __global__ void __launch_bounds__(ProjTile<D>::NT)
 k_proj_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
              typename Storage<S>::T *__restrict__ Fo, typename Storage<S>::T *__restrict__ Bo,
              const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
-             StepConst<typename Storage<S>::C> k, Codec cd) {
+             StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag) {
     using C = typename Storage<S>::C;
     using TL = ProjTile<D>;
     constexpr bool STAGED = !GATHERED && D == 2;
     __shared__ C lsrc[ProjSet<D>::NSP * TL::HN];
     __shared__ C lb[STAGED ? ProjLayout<D, TH>::NBP * TL::BN : 1];
-    proj_tile_step<S, D, TH, GATHERED, TL>(F, B, Fo, Bo, Tf, Tconst, g, k, cd, blockIdx.x, blockIdx.y, lsrc, lb);
+    proj_tile_step<S, D, TH, GATHERED, TL>(F, B, Fo, Bo, Tf, Tconst, g, k, cd, blockIdx.x, blockIdx.y, lsrc, lb, flag);
 }
 
 // ---- health of a projected lattice: non-finite sites, rho <= 0 sites, max |u*| -----------------
@@ -558,7 +590,8 @@ k_proj_readout(const typename Storage<S>::T *__restrict__ F, const typename Stor
 }
 
 // ---- initialisation: class sums of feq(rho, u) and the reduced beq(u, T) (gathered) -------------
-// Transverse velocity components must be zero; a site with one sets *flag.
+// Transverse velocity components must be zero; a site with one sets bit 2 of *flag (bit 1: a
+// 16-bit code overflowed).
 template <int S, int D, bool TH, typename IN>
 __global__ void __launch_bounds__(BLOCK)
 k_proj_init(const IN *__restrict__ rho, const IN *__restrict__ u, const IN *__restrict__ T, Geo g, double rho_ref,
@@ -571,7 +604,7 @@ k_proj_init(const IN *__restrict__ rho, const IN *__restrict__ u, const IN *__re
     if (s >= g.n) return;
     const size_t n = g.n;
     const double r = (double)rho[s], ux = (double)u[s], uy = (double)u[n + s], uz = (double)u[2 * n + s];
-    if (uz != 0.0 || (D == 1 && uy != 0.0)) *flag = 2u;
+    if (uz != 0.0 || (D == 1 && uy != 0.0)) atomicOr(flag, 2u);
     const double theta = (double)T[s] - T_ref;
     double f[Q], b[NB];
     equilibrium_dev(r - rho_ref, r, ux, D == 2 ? uy : 0.0, 0.0, f);
@@ -580,14 +613,15 @@ k_proj_init(const IN *__restrict__ rho, const IN *__restrict__ u, const IN *__re
     proj_contract<D, TH>(f, b, dF, dG, bred);
     unsigned sat = 0;
 #pragma unroll
-    for (int c = 0; c < PS::NC; c++) Storage<S>::store(F, (size_t)c * n + s, 0, (C)dF[c], cd, sat);
+    for (int c = 0; c < PS::NC; c++) proj_st<S>(F, (size_t)c * n + s, (C)dF[c], sat);
     if constexpr (TH) {
 #pragma unroll
-        for (int c = 0; c < PS::NG; c++) Storage<S>::store(F, (size_t)(PS::NC + c) * n + s, 0, (C)dG[c], cd, sat);
+        for (int c = 0; c < PS::NG; c++) proj_st<S>(F, (size_t)(PS::NC + c) * n + s, (C)dG[c], sat);
     }
 #pragma unroll
-    for (int kk = 0; kk < PL::NBP; kk++) Storage<S>::store(B, (size_t)kk * n + s, 0, (C)bred[kk], cd, sat);
+    for (int kk = 0; kk < PL::NBP; kk++) proj_st<S>(B, (size_t)kk * n + s, (C)bred[kk], sat);
     if (Tf) Tf[s] = (C)theta;
+    if (sat) atomicOr(flag, 1u);
 }
 
 // ---- decoded state in FP64: full class sums and gathered reduced bbar ----------------------------

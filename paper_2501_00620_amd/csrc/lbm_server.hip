@@ -13,10 +13,10 @@
 // whose steps are done (health check, moments to host, memory freed), and timestamps each
 // request.  Requests submitted while a bundle runs wait at most one bundle for admission.
 //
-// With FP32 storage, a one-plane request without transverse velocity is served as a projected
-// D2Q9 lattice (lbm_set_projection): the same step on 18 (THERMAL) or 12 (ISO) values per site
-// instead of 25, swept by k_serve_proj.  Its result is what the same lattice stepped alone with
-// that projection gives, to the bit.
+// With FP32 or BF16 storage, a one-plane request without transverse velocity is served as a
+// projected D2Q9 lattice (lbm_set_projection): the same step on 18 (THERMAL) or 12 (ISO) values
+// per site instead of 25, swept by k_serve_proj.  Its result is what the same lattice stepped
+// alone with that projection gives, to the bit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -92,15 +92,17 @@ k_serve(const ServeDesc *__restrict__ descs, const TileRef *__restrict__ tiles, 
     }
 }
 
-// Projected D2Q9 lattices (FP32): tiles [ntiles[1], ntiles[2]) of the table.  The per-tile step
+// Projected D2Q9 lattices (FP32 or BF16): tiles [ntiles[1], ntiles[2]) of the table.  The per-tile step
 // and the tiles are those of the one-launch kernel of a lattice stepped alone, so the results
 // agree to the bit: which sites of a tile are ring sites decides how the compiler may fuse their
 // source arithmetic, so another tile shape would change the last bit.
 using ProjServeTile = ProjTile<2>;
+template <int S>
 __global__ void __launch_bounds__(ProjServeTile::NT)
 k_serve_proj(const ServeDesc *__restrict__ descs, const TileRef *__restrict__ tiles, const int *__restrict__ ntiles,
              int step) {
     using TL = ProjServeTile;
+    using T = typename Storage<S>::T;
     __shared__ float lsrc[ProjSet<2>::NSP * TL::HN];
     __shared__ float lb[ProjLayout<2, true>::NBP * TL::BN];
     for (int t = ntiles[1] + (int)blockIdx.x; t < ntiles[2]; t += (int)gridDim.x) {
@@ -109,12 +111,14 @@ k_serve_proj(const ServeDesc *__restrict__ descs, const TileRef *__restrict__ ti
         if (step >= d.steps_left) continue;  // this lattice is done for the bundle (uniform)
         const int cur = (d.cur0 + step) & 1;
         const int bx = e.tile % d.fg.tiles_x, by = e.tile / d.fg.tiles_x;
-        const float *F = (const float *)d.F[cur], *B = (const float *)d.B[cur];
-        float *Fo = (float *)d.F[1 - cur], *Bo = (float *)d.B[1 - cur];
+        const T *F = (const T *)d.F[cur], *B = (const T *)d.B[cur];
+        T *Fo = (T *)d.F[1 - cur], *Bo = (T *)d.B[1 - cur];
         if (d.k.iso)
-            proj_tile_step<1, 2, false, false, TL>(F, B, Fo, Bo, d.Tf, d.Tconst, d.g, d.k, d.cd, bx, by, lsrc, lb);
+            proj_tile_step<S, 2, false, false, TL>(F, B, Fo, Bo, d.Tf, d.Tconst, d.g, d.k, d.cd, bx, by, lsrc, lb,
+                                                   d.flag);
         else
-            proj_tile_step<1, 2, true, false, TL>(F, B, Fo, Bo, d.Tf, d.Tconst, d.g, d.k, d.cd, bx, by, lsrc, lb);
+            proj_tile_step<S, 2, true, false, TL>(F, B, Fo, Bo, d.Tf, d.Tconst, d.g, d.k, d.cd, bx, by, lsrc, lb,
+                                                  d.flag);
         __syncthreads();  // the next tile reuses the LDS
     }
 }
@@ -196,10 +200,10 @@ void fail_request(lbm_server *s, Request &r, const std::string &msg) {
     s->n_failed++;
 }
 
-// A request is served as a projected D2Q9 lattice when the storage is FP32 and the lattice is
-// one plane with no transverse velocity.
+// A request is served as a projected D2Q9 lattice when the storage is FP32 or BF16 and the
+// lattice is one plane with no transverse velocity.
 bool serve_projected(const lbm_server *s, const Request &r) {
-    if (s->prm.storage != LBM_F32 || r.p.nz != 1 || r.p.mode == LBM_STANDARD) return false;
+    if (s->prm.storage == LBM_F16DEV || r.p.nz != 1 || r.p.mode == LBM_STANDARD) return false;
     const size_t n = (size_t)r.p.nx * r.p.ny;
     for (size_t i = 0; i < n; i++)
         if (r.u[2 * n + i] != 0.0) return false;
@@ -365,9 +369,11 @@ int capture_graph(lbm_server *s) {
             if (gen)
                 hipLaunchKernelGGL((k_serve<S, false>), dim3(s->grid), dim3(ServeTile<S, false>::NT), 0, s->stream, s->d_desc,
                                    s->d_tiles, s->d_ntiles, st);
-            if (proj)
-                hipLaunchKernelGGL(k_serve_proj, dim3(s->grid_proj), dim3(ProjServeTile::NT), 0, s->stream, s->d_desc,
-                                   s->d_tiles, s->d_ntiles, st);
+            if constexpr (S != 2) {
+                if (proj)
+                    hipLaunchKernelGGL((k_serve_proj<S>), dim3(s->grid_proj), dim3(ProjServeTile::NT), 0, s->stream,
+                                       s->d_desc, s->d_tiles, s->d_ntiles, st);
+            }
         }
         return LBM_OK;
     });
@@ -537,7 +543,7 @@ int lbm_server_create(const lbm_server_params *p, void *hip_stream, lbm_server_h
     });
     s->grid_thin = cus * (per_cu > 0 ? per_cu : 1);
     int per_cu_proj = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_proj, k_serve_proj, ProjServeTile::NT, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_proj, k_serve_proj<1>, ProjServeTile::NT, 0) != hipSuccess)
         per_cu_proj = 1;
     s->grid_proj = cus * (per_cu_proj > 0 ? per_cu_proj : 1);
     if (hip_stream) {
