@@ -176,13 +176,13 @@ int lbm_set_walls(lbm_handle h, int on, const double *u_bottom, const double *u_
  * Per site the state is 12 values (D2Q9, ISO), 18 (D2Q9, THERMAL), 4 (D1Q3, ISO) or 8
  * (D1Q3, THERMAL), in place of 25.  The call frees the state (set_fields again) and
  * reallocates the buffers.
- * Supports: modes THERMAL and ISO; storage F64, F32 and BF16DEV (its codes hold the deviation
- * itself; F16DEV, whose codes need per-field scales, is refused); lbm_set_fields (the
+ * Supports: modes THERMAL and ISO; every storage (F16DEV takes one scale per plane, chosen at
+ * lbm_set_fields from the class-summed bound of the initial deviations); lbm_set_fields (the
  * transverse velocity must be 0), lbm_step, lbm_get_moments (transverse u = 0),
  * lbm_get_state (see lbm_get_projection for its layout) and lbm_health.  lbm_set_state,
  * lbm_get_stored, lbm_invariants, walls, body force, a ghost rate and the fused kernel return
  * ARG.
- * Errors: ARG (dims, lattice shape, mode, storage, one of those settings), OOM, HIP. */
+ * Errors: ARG (dims, lattice shape, mode, one of those settings), OOM, HIP. */
 int lbm_set_projection(lbm_handle h, int dims);
 
 /* The projection of a lattice and its lbm_get_state layout.
@@ -213,8 +213,8 @@ size_t lbm_lattice_bytes(const lbm_params *p);
 /* ---------------------------------------------------------------------------------------------
  * Serving: continuous batching of many independent lattices on one GPU.
  *
- * With F32 or BF16DEV storage, a one-plane request (nz = 1) without transverse velocity is held
- * as a projected D2Q9 lattice (lbm_set_projection).  Its result is what that lattice gives stepped
+ * A one-plane request (nz = 1) without transverse velocity is held as a projected D2Q9 lattice
+ * (lbm_set_projection).  Its result is what that lattice gives stepped
  * alone with the projection, to the bit; every other request is what the D3Q19 lattice gives
  * stepped alone with the fused kernel.
  *

@@ -121,6 +121,42 @@ void choose_scales(lbm_lattice *h, const double *absmax) {
     }
 }
 
+// FP16 scales of a projected lattice: each plane's initial deviation is bounded by the sum of its
+// members' (class sums; transverse-weighted for G), the variance planes by their components'.
+// Then the same power-of-two choice as choose_scales.  Fields: class sum c at c, its G at
+// NC + c, variance plane k at Q + k.
+template <int D> void choose_scales_proj(lbm_lattice *h, const double *absmax) {
+    using PS = ProjSet<D>;
+    const bool th = h->p.mode == LBM_THERMAL;
+    double am[NFIELD], fl[NFIELD];
+    for (int k = 0; k < NFIELD; k++) am[k] = 0.0, fl[k] = 1e-3;
+    for (int i = 0; i < Q; i++) {
+        const int c = PS::CLS[i];
+        am[c] += absmax[i];
+        if (th && et2<D>(i) > 0) am[PS::NC + c] += et2<D>(i) * absmax[i];
+    }
+    for (int c = 0; c < PS::NC; c++) {
+        fl[c] = 1e-3 * class_w<D>(c) * h->p.rho_ref;
+        if (c < PS::NG) fl[PS::NC + c] = 1e-3 * class_gw<D>(c) * h->p.rho_ref;
+    }
+    if constexpr (D == 2) {
+        am[Q + 0] = absmax[Q + 0];
+        am[Q + 1] = absmax[Q + 1];
+        am[Q + 2] = absmax[Q + 3];
+        am[Q + 3] = absmax[Q + 2];
+    } else {
+        am[Q + 0] = absmax[Q + 0];
+        am[Q + 1] = absmax[Q + 1] + absmax[Q + 2];
+    }
+    const double target = 65504.0 / 1024.0;
+    for (int k = 0; k < NFIELD; k++) {
+        const double m = am[k] > fl[k] ? am[k] : fl[k];
+        const double sc = std::ldexp(1.0, (int)std::ceil(std::log2(m / target)));
+        h->codec.scale[k] = (float)sc;
+        h->codec.inv[k] = (float)(1.0 / sc);
+    }
+}
+
 template <typename Fn> int dispatch_storage(int storage, Fn &&fn) {
     switch (storage) {
     case LBM_F64: return fn(std::integral_constant<int, 0>{});
@@ -131,21 +167,16 @@ template <typename Fn> int dispatch_storage(int storage, Fn &&fn) {
     return fail(LBM_ERR_ARG, "unknown storage %d", storage);
 }
 
-// Projected lattices (lbm_set_projection): F64, F32 or BF16 storage (BF16 codes hold the deviation
-// itself: no per-field scale), D = 2 or 1, energy-conserving or not.
+// Projected lattices (lbm_set_projection): any storage, D = 2 or 1, energy-conserving or not.
 template <typename Fn> int dispatch_proj(const lbm_lattice *h, Fn &&fn) {
     using D2 = std::integral_constant<int, 2>;
     using D1 = std::integral_constant<int, 1>;
     const bool th = h->p.mode == LBM_THERMAL;
     return dispatch_storage(h->p.storage, [&](auto SI) -> int {
         constexpr int S = decltype(SI)::value;
-        if constexpr (S == 2) {
-            return fail(LBM_ERR_ARG, "projected lattices store F64, F32 or BF16");
-        } else {
-            if (h->proj == 2)
-                return th ? fn(SI, D2{}, std::true_type{}) : fn(SI, D2{}, std::false_type{});
-            return th ? fn(SI, D1{}, std::true_type{}) : fn(SI, D1{}, std::false_type{});
-        }
+        if (h->proj == 2)
+            return th ? fn(SI, D2{}, std::true_type{}) : fn(SI, D2{}, std::false_type{});
+        return th ? fn(SI, D1{}, std::true_type{}) : fn(SI, D1{}, std::false_type{});
     });
 }
 
@@ -445,8 +476,6 @@ int lbm_set_projection(lbm_handle h, int dims) {
     if (dims == 1 && (h->p.ny != 1 || h->p.nz != 1)) return fail(LBM_ERR_ARG, "a D1Q3 projection needs ny = nz = 1");
     if (dims < 3) {
         if (h->p.mode == LBM_STANDARD) return fail(LBM_ERR_ARG, "the standard comparator is not projected");
-        if (h->p.storage == LBM_F16DEV)
-            return fail(LBM_ERR_ARG, "projected lattices store F64, F32 or BF16 (FP16 codes need per-field scales)");
         if (h->kernel == 2) return fail(LBM_ERR_ARG, "projected lattices step with their own two-pass kernels");
         if (h->walls || h->accel || h->tau_ghost > 0.0)
             return fail(LBM_ERR_ARG, "projected lattices have no walls, body force or ghost rate");
@@ -608,7 +637,11 @@ int lbm_set_fields(lbm_handle h, const void *rho, const void *u, const void *T, 
     if (!rc) rc = finish_reduction<true>(h, rb, NFIELD + 1, absmax);
     if (!rc && absmax[NFIELD] > 0) rc = fail(LBM_ERR_ARG, "fields contain rho <= 0 or non-finite values");
     if (!rc) {
-        choose_scales(h, absmax);
+        if (h->proj < 3 && h->p.storage == LBM_F16DEV) {
+            if (h->proj == 2) choose_scales_proj<2>(h, absmax); else choose_scales_proj<1>(h, absmax);
+        } else {
+            choose_scales(h, absmax);
+        }
         // ISO: keep a per-site temperature field only if it is not uniform
         if (h->Tf) {
             (void)hipFree(h->Tf);

@@ -20,8 +20,8 @@
 // nine in-plane offsets for D = 2, the two x offsets for D = 1), which is what the D3Q19 stencil
 // reduces to when the transverse neighbours are the site's own column.
 //
-// Stored per site (deviations from the references; storage F64, F32, or BF16 deviation codes,
-// which hold the deviation itself and so need no per-field scale):
+// Stored per site (deviations from the references; storage F64, F32, or 16-bit deviation codes:
+// BF16 holds the deviation itself, FP16 a power-of-two-scaled deviation per plane):
 //   F planes: dF_c for the NC classes, then dG_c for the NG classes with transverse members
 //             (energy-conserving mode only)
 //   B planes: the in-plane bbar deviations (D = 2: xx yy xy; D = 1: xx), then the transverse trace
@@ -49,21 +49,27 @@ template <> struct ProjSet<1> {
     static constexpr int CY[NC] = {0, 0, 0};
 };
 
-// Loads and stores of the projected state.  BF16 codes hold the deviation itself (their scale is
-// always 1), so no codec is read: in the server the codec sits in a descriptor in device memory,
-// and a scale multiply per access would reload it around every store.
-template <int S> __device__ __forceinline__ typename Storage<S>::C proj_ld(const typename Storage<S>::T *p, size_t i) {
-    static_assert(S != 2, "FP16 codes need per-field scales");
+// Loads and stores of the projected state; f is the plane's codec field (class sum c: c; its G:
+// NC + c; variance plane k: Q + k).  BF16 codes hold the deviation itself (their scale is always
+// 1), so they read no codec: in the server the codec sits in a descriptor in device memory.
+// FP16 codes use the field's power-of-two scale, chosen at lbm_set_fields.
+template <int S>
+__device__ __forceinline__ typename Storage<S>::C proj_ld(const typename Storage<S>::T *p, size_t i, int f,
+                                                          const Codec &cd) {
     if constexpr (S == 3)
         return bf16_bits_to_float(p[i]);
+    else if constexpr (S == 2)
+        return Storage<2>::load(p, i, f, cd);
     else
         return p[i];
 }
 template <int S>
-__device__ __forceinline__ void proj_st(typename Storage<S>::T *p, size_t i, typename Storage<S>::C v, unsigned &sat) {
-    static_assert(S != 2, "FP16 codes need per-field scales");
+__device__ __forceinline__ void proj_st(typename Storage<S>::T *p, size_t i, typename Storage<S>::C v, int f,
+                                        const Codec &cd, unsigned &sat) {
     if constexpr (S == 3)
         p[i] = float_to_bf16_bits(v, sat);
+    else if constexpr (S == 2)
+        Storage<2>::store(p, i, f, v, cd, sat);
     else
         p[i] = v;
 }
@@ -175,14 +181,14 @@ __device__ __forceinline__ void proj_load(const typename Storage<S>::T *__restri
     using PL = ProjLayout<D, TH>;
     C dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP];
 #pragma unroll
-    for (int c = 0; c < PS::NC; c++) dF[c] = proj_ld<S>(F, (size_t)c * n + s);
+    for (int c = 0; c < PS::NC; c++) dF[c] = proj_ld<S>(F, (size_t)c * n + s, c, cd);
     if constexpr (TH) {
 #pragma unroll
-        for (int c = 0; c < PS::NG; c++) dG[c] = proj_ld<S>(F, (size_t)(PS::NC + c) * n + s);
+        for (int c = 0; c < PS::NG; c++) dG[c] = proj_ld<S>(F, (size_t)(PS::NC + c) * n + s, PS::NC + c, cd);
     }
     if constexpr (GATHERED) {
 #pragma unroll
-        for (int k = 0; k < PL::NBP; k++) bred[k] = proj_ld<S>(B, (size_t)k * n + s);
+        for (int k = 0; k < PL::NBP; k++) bred[k] = proj_ld<S>(B, (size_t)k * n + s, Q + k, cd);
     } else {
         C acc[PL::NBP], rho = rho_ref;
 #pragma unroll
@@ -192,7 +198,7 @@ __device__ __forceinline__ void proj_load(const typename Storage<S>::T *__restri
             const C wgt = fma(C(class_w<D>(c)), rho_ref, dF[c]);
             rho += dF[c];
 #pragma unroll
-            for (int k = 0; k < PL::NBP; k++) acc[k] += wgt * proj_ld<S>(B, (size_t)k * n + up);
+            for (int k = 0; k < PL::NBP; k++) acc[k] += wgt * proj_ld<S>(B, (size_t)k * n + up, Q + k, cd);
         });
         const C inv = recip(rho);
 #pragma unroll
@@ -302,12 +308,12 @@ k_proj_collide(const typename Storage<S>::T *__restrict__ F, const typename Stor
     unsigned sat = 0;
     Unroll<0, PS::NC>::run([&](auto c) {
         const int to = proj_at(nb, PS::CX[c], PS::CY[c]);
-        proj_st<S>(Fo, (size_t)c * g.n + to, dF[c], sat);
-        if constexpr (TH && c < PS::NG) proj_st<S>(Fo, (size_t)(PS::NC + c) * g.n + to, dG[c], sat);
+        proj_st<S>(Fo, (size_t)c * g.n + to, dF[c], c, cd, sat);
+        if constexpr (TH && c < PS::NG) proj_st<S>(Fo, (size_t)(PS::NC + c) * g.n + to, dG[c], PS::NC + c, cd, sat);
     });
 #pragma unroll
-    for (int kk = 0; kk < PL::NBP; kk++) proj_st<S>(Bo, (size_t)kk * g.n + s, bred[kk], sat);
-    if constexpr (S == 3) proj_flag_overflow(flag, sat);
+    for (int kk = 0; kk < PL::NBP; kk++) proj_st<S>(Bo, (size_t)kk * g.n + s, bred[kk], Q + kk, cd, sat);
+    if constexpr (S >= 2) proj_flag_overflow(flag, sat);
 }
 
 // ---- one-launch step: sources of a tile and its one-site halo in LDS -------------------------------
@@ -377,10 +383,10 @@ __device__ __forceinline__ void proj_tile_site(const typename Storage<S>::T *__r
         const size_t n = g.n;
         C dF[PS::NC], dG[TH ? PS::NG : 1], bred[PL::NBP], acc[PL::NBP], rho = k.rho_ref;
 #pragma unroll
-        for (int c = 0; c < PS::NC; c++) dF[c] = proj_ld<S>(F, (size_t)c * n + s);
+        for (int c = 0; c < PS::NC; c++) dF[c] = proj_ld<S>(F, (size_t)c * n + s, c, cd);
         if constexpr (TH) {
 #pragma unroll
-            for (int c = 0; c < PS::NG; c++) dG[c] = proj_ld<S>(F, (size_t)(PS::NC + c) * n + s);
+            for (int c = 0; c < PS::NG; c++) dG[c] = proj_ld<S>(F, (size_t)(PS::NC + c) * n + s, PS::NC + c, cd);
         }
 #pragma unroll
         for (int kk = 0; kk < PL::NBP; kk++) acc[kk] = C(0);
@@ -441,7 +447,7 @@ __device__ __forceinline__ void proj_tile_step(const typename Storage<S>::T *__r
             const int x = wrap_mod(x0 - 2 + l % TL::BX, g.nx), y = wrap_mod(y0 - 2 * TL::HY + l / TL::BX, g.ny);
             const int s = y * g.nx + x;
 #pragma unroll
-            for (int kk = 0; kk < PL::NBP; kk++) lb[kk * TL::BN + l] = proj_ld<S>(B, (size_t)kk * n + s);
+            for (int kk = 0; kk < PL::NBP; kk++) lb[kk * TL::BN + l] = proj_ld<S>(B, (size_t)kk * n + s, Q + kk, cd);
         }
         __syncthreads();
     }
@@ -504,12 +510,12 @@ __device__ __forceinline__ void proj_tile_step(const typename Storage<S>::T *__r
         unsigned sat = 0;
         Unroll<0, PS::NC>::run([&](auto c) {
             const int to = proj_at(nb, PS::CX[c], PS::CY[c]);
-            proj_st<S>(Fo, (size_t)c * n + to, dF[c], sat);
-            if constexpr (TH && c < PS::NG) proj_st<S>(Fo, (size_t)(PS::NC + c) * n + to, dG[c], sat);
+            proj_st<S>(Fo, (size_t)c * n + to, dF[c], c, cd, sat);
+            if constexpr (TH && c < PS::NG) proj_st<S>(Fo, (size_t)(PS::NC + c) * n + to, dG[c], PS::NC + c, cd, sat);
         });
 #pragma unroll
-        for (int kk = 0; kk < PL::NBP; kk++) proj_st<S>(Bo, (size_t)kk * n + s, bred[kk], sat);
-        if constexpr (S == 3) proj_flag_overflow(flag, sat);
+        for (int kk = 0; kk < PL::NBP; kk++) proj_st<S>(Bo, (size_t)kk * n + s, bred[kk], Q + kk, cd, sat);
+        if constexpr (S >= 2) proj_flag_overflow(flag, sat);
     }
 }
 
@@ -613,13 +619,13 @@ k_proj_init(const IN *__restrict__ rho, const IN *__restrict__ u, const IN *__re
     proj_contract<D, TH>(f, b, dF, dG, bred);
     unsigned sat = 0;
 #pragma unroll
-    for (int c = 0; c < PS::NC; c++) proj_st<S>(F, (size_t)c * n + s, (C)dF[c], sat);
+    for (int c = 0; c < PS::NC; c++) proj_st<S>(F, (size_t)c * n + s, (C)dF[c], c, cd, sat);
     if constexpr (TH) {
 #pragma unroll
-        for (int c = 0; c < PS::NG; c++) proj_st<S>(F, (size_t)(PS::NC + c) * n + s, (C)dG[c], sat);
+        for (int c = 0; c < PS::NG; c++) proj_st<S>(F, (size_t)(PS::NC + c) * n + s, (C)dG[c], PS::NC + c, cd, sat);
     }
 #pragma unroll
-    for (int kk = 0; kk < PL::NBP; kk++) proj_st<S>(B, (size_t)kk * n + s, (C)bred[kk], sat);
+    for (int kk = 0; kk < PL::NBP; kk++) proj_st<S>(B, (size_t)kk * n + s, (C)bred[kk], Q + kk, cd, sat);
     if (Tf) Tf[s] = (C)theta;
     if (sat) atomicOr(flag, 1u);
 }

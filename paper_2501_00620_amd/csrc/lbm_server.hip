@@ -13,8 +13,7 @@
 // whose steps are done (health check, moments to host, memory freed), and timestamps each
 // request.  Requests submitted while a bundle runs wait at most one bundle for admission.
 //
-// With FP32 or BF16 storage, a one-plane request without transverse velocity is served as a
-// projected D2Q9 lattice (lbm_set_projection): the same step on 18 (THERMAL) or 12 (ISO) values
+// A one-plane request without transverse velocity is served as a projected D2Q9 lattice (lbm_set_projection): the same step on 18 (THERMAL) or 12 (ISO) values
 // per site instead of 25, swept by k_serve_proj.  Its result is what the same lattice stepped
 // alone with that projection gives, to the bit.
 #include <hip/hip_runtime.h>
@@ -92,7 +91,7 @@ k_serve(const ServeDesc *__restrict__ descs, const TileRef *__restrict__ tiles, 
     }
 }
 
-// Projected D2Q9 lattices (FP32 or BF16): tiles [ntiles[1], ntiles[2]) of the table.  The per-tile step
+// Projected D2Q9 lattices: tiles [ntiles[1], ntiles[2]) of the table.  The per-tile step
 // and the tiles are those of the one-launch kernel of a lattice stepped alone, so the results
 // agree to the bit: which sites of a tile are ring sites decides how the compiler may fuse their
 // source arithmetic, so another tile shape would change the last bit.
@@ -200,10 +199,11 @@ void fail_request(lbm_server *s, Request &r, const std::string &msg) {
     s->n_failed++;
 }
 
-// A request is served as a projected D2Q9 lattice when the storage is FP32 or BF16 and the
-// lattice is one plane with no transverse velocity.
+// A request is served as a projected D2Q9 lattice when the lattice is one plane with no
+// transverse velocity.
 bool serve_projected(const lbm_server *s, const Request &r) {
-    if (s->prm.storage == LBM_F16DEV || r.p.nz != 1 || r.p.mode == LBM_STANDARD) return false;
+    (void)s;
+    if (r.p.nz != 1 || r.p.mode == LBM_STANDARD) return false;
     const size_t n = (size_t)r.p.nx * r.p.ny;
     for (size_t i = 0; i < n; i++)
         if (r.u[2 * n + i] != 0.0) return false;
@@ -369,11 +369,9 @@ int capture_graph(lbm_server *s) {
             if (gen)
                 hipLaunchKernelGGL((k_serve<S, false>), dim3(s->grid), dim3(ServeTile<S, false>::NT), 0, s->stream, s->d_desc,
                                    s->d_tiles, s->d_ntiles, st);
-            if constexpr (S != 2) {
-                if (proj)
-                    hipLaunchKernelGGL((k_serve_proj<S>), dim3(s->grid_proj), dim3(ProjServeTile::NT), 0, s->stream,
-                                       s->d_desc, s->d_tiles, s->d_ntiles, st);
-            }
+            if (proj)
+                hipLaunchKernelGGL((k_serve_proj<S>), dim3(s->grid_proj), dim3(ProjServeTile::NT), 0, s->stream,
+                                   s->d_desc, s->d_tiles, s->d_ntiles, st);
         }
         return LBM_OK;
     });
@@ -543,8 +541,13 @@ int lbm_server_create(const lbm_server_params *p, void *hip_stream, lbm_server_h
     });
     s->grid_thin = cus * (per_cu > 0 ? per_cu : 1);
     int per_cu_proj = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_proj, k_serve_proj<1>, ProjServeTile::NT, 0) != hipSuccess)
-        per_cu_proj = 1;
+    (void)dispatch_serve(p->storage, [&](auto SI) -> int {
+        constexpr int S = decltype(SI)::value;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_proj, k_serve_proj<S>, ProjServeTile::NT, 0) !=
+            hipSuccess)
+            per_cu_proj = 1;
+        return 0;
+    });
     s->grid_proj = cus * (per_cu_proj > 0 ? per_cu_proj : 1);
     if (hip_stream) {
         s->stream = (hipStream_t)hip_stream;

@@ -28,9 +28,9 @@ def alone(fields, tau, steps, storage, mode="thermal"):
     rho, u, T = fields
     nz, ny, nx = rho.shape
     rho_ref, T_ref = lbm().codec_reference(rho, T)  # the server's default reference
-    # the server holds an FP32 or BF16 one-plane lattice without transverse velocity as a
-    # projected D2Q9 lattice; alone, the same projection steps it
-    projected = storage in ("f32", "bf16dev") and nz == 1 and not np.any(np.asarray(u)[2])
+    # the server holds a one-plane lattice without transverse velocity as a projected D2Q9
+    # lattice; alone, the same projection steps it
+    projected = nz == 1 and not np.any(np.asarray(u)[2])
     g = lbm().Lattice(nx, ny, nz, tau, storage=storage, mode=mode, kernel="auto" if projected else "fused",
                       rho_ref=rho_ref, T_ref=T_ref)
     if projected:
