@@ -559,6 +559,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-only", action="store_true", help="run only the served-batch workload")
+    ap.add_argument("--projections-only", action="store_true", help="run only the projected-lattice workload")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -577,6 +578,9 @@ def main():
     from paper_2501_00620_amd import lbm, workloads
     if args.serve_only:
         print(json.dumps({"served": run_served_comparison(n_requests=args.serve_requests)}))
+        return
+    if args.projections_only:
+        print(json.dumps({"projections": projections()}))
         return
     n, tau, mach = args.n, 0.55, 0.5
     rho, u, T = workloads.taylor_green(n, mach=mach)
