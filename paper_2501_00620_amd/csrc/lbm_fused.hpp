@@ -8,14 +8,14 @@
 //   1. stages the post-collision bbar* of plane z+2 over the tile plus two rings in LDS
 //      (coalesced loads; each value is then read by up to 19 gathers from LDS);
 //   2. evaluates the sources of plane z+1 on the tile plus a one-site ring (the ring overlaps
-//      the neighbouring tiles) into one of three LDS source planes, keeping the tile's own
-//      populations, bbar and moments in registers for the next iteration;
+//      the neighbouring tiles) into one of three LDS source planes, keeping the tile's gathered
+//      bbar in registers and part of its populations in LDS for the next iteration;
 //   3. takes the isotropic gradients of plane z from the source planes z-1, z, z+1, collides
 //      the registers kept from the previous iteration, and pushes the results out.
 // The algorithmic minimum is 2 x 25 values per lattice update: each site's state read once and
 // written once.  On top of it come the ring sites (neighbouring tiles on the same XCD bring them
-// into L2 at about the same time) and the collision's second read of the tile's populations
-// (an L2 hit unless the stream in between evicted them).  The staging and source loads are
+// into L2 at about the same time) and the collision's second read of the tile's populations not
+// kept in LDS (an L2 hit unless the stream in between evicted them).  The staging and source loads are
 // issued one plane iteration ahead of their use.
 //
 // Work-groups are numbered so that the ones dispatched to one XCD (block index mod 8) take
@@ -36,6 +36,19 @@ namespace lbm {
 #endif
 #ifndef GATHER_GROUP
 #define GATHER_GROUP 5  // directions per scheduling group in the gather
+#endif
+// Populations of the tile's own sites kept in LDS from the source evaluation to the collision
+// one plane later, per storage (FP32, FP16 deviation, BF16 deviation): the first N of the 19,
+// as many as fit the LDS beside the source and staging planes, or fewer where more measured
+// slower.  The rest are read again at the collision.
+#ifndef FUSED_STASH_F32
+#define FUSED_STASH_F32 8
+#endif
+#ifndef FUSED_STASH_F16
+#define FUSED_STASH_F16 8
+#endif
+#ifndef FUSED_STASH_BF16
+#define FUSED_STASH_BF16 16
 #endif
 
 template <int TX_, int TY_> struct Tile {
@@ -58,6 +71,11 @@ template <int TX_, int TY_> struct Tile {
 #endif
 template <int S> struct TileFor { using type = Tile<FUSED_TX, FUSED_TY>; };
 template <> struct TileFor<0> { using type = Tile<64, 2>; };
+// populations kept in LDS by the marching single-lattice kernel (none in double precision, whose
+// LDS is full, and none in the one-plane kernel, which runs several work-groups per CU)
+template <int S> constexpr int fused_stash() {
+    return S == 0 ? 0 : (S == 1 ? FUSED_STASH_F32 : (S == 2 ? FUSED_STASH_F16 : FUSED_STASH_BF16));
+}
 // Tiles of the one-plane serving kernel.  With one LDS slot of each kind (43 KB) and the in-plane
 // arithmetic it fits 128 VGPRs, so two 512-thread work-groups share a CU (four waves per SIMD),
 // each covering the other's load waits.
@@ -159,8 +177,9 @@ template <int S> struct Buf {
 
 // What a thread carries from the source evaluation of its site to the site's collision one
 // plane later: the gathered bbar (which cannot be re-gathered then, its upstream plane is no
-// longer staged) and the ISO temperature offset.  The populations are re-read at the collision
-// (the same work-group read them one plane earlier, so they come from L2).
+// longer staged) and the ISO temperature offset.  The populations travel in LDS as far as it
+// has room (NST of them, as loaded); the others are read again at the collision (the same
+// work-group read them one plane earlier, so they mostly come from L2).
 template <typename C> struct SiteState {
     C beta[NB];
     C theta;
@@ -269,8 +288,9 @@ __device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typen
 // single-lattice kernel and the multi-lattice serving kernel.  HASK: T_ref != 1/3 (the constant
 // part of rho b enters the second-moment source).  THIN1: the lattice has exactly one z plane
 // (one LDS slot of each kind, about a third of the LDS, so that several work-groups share a CU).
-// amax collects |16-bit codes| stored.
-template <int S, bool GATHERED, bool HASK, bool THIN1 = false, typename TL = typename TileFor<S>::type>
+// amax collects |16-bit codes| stored.  NST_: populations of the tile's own sites carried in
+// LDS from the source evaluation to the collision (staged kernels only).
+template <int S, bool GATHERED, bool HASK, bool THIN1 = false, typename TL = typename TileFor<S>::type, int NST_ = 0>
 __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restrict__ F,
                                            const typename Storage<S>::T *__restrict__ B,
                                            typename Storage<S>::T *__restrict__ Fo,
@@ -287,6 +307,10 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
     constexpr int NSLOT = THIN1 ? 1 : 3;
     __shared__ C lds[NSLOT][NSRC * NS];
     __shared__ C bst[GATHERED ? 1 : NSLOT][GATHERED ? 1 : NB * NB2];
+    // two slots by plane parity: the sources of plane z+1 are evaluated before plane z collides
+    constexpr int NST = GATHERED ? 0 : NST_;
+    __shared__ typename Buf<S>::R pst[NST > 0 ? 2 * NST * TL::NT : 1];
+    (void)pst;
 
     Buf<S> bF, bB, bFo, bBo;
     bF.init(F, Q, g.n);
@@ -444,6 +468,10 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
             // ring populations not loaded one plane ahead are loaded just before their use
             // (issued before the tile's own sources, they cost more registers than they save)
             constexpr bool ahead = PIPE && FUSED_PREFETCH_RING;
+            if constexpr (NST > 0) {
+                typename Buf<S>::R *ps = pst + ((p - z0) & 1) * NST * TL::NT + threadIdx.x;
+                Unroll<0, NST>::run([&](auto I) { ps[I * TL::NT] = praw[I]; });
+            }
             source_site_staged<S, TL, true, THIN1>(bF, praw, Tf, Tconst, k, cd, zo + ixy, ibidx, bs, lds[slot], iidx, keep);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -472,7 +500,18 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
         const int wz = wrapc(z, g.nz);
         const int zc = wz * nxy;
         C d[Q];
-        load_pops<S>(bF, (zc + ixy) * SB, cd, d);  // issued early, consumed after the gradient
+        if constexpr (NST > 0) {
+            // the first NST as the source evaluation of this plane left them in LDS, the rest
+            // read again (issued early, consumed after the gradient)
+            const typename Buf<S>::R *ps = pst + ((z - z0) & 1) * NST * TL::NT + threadIdx.x;
+            const int off = (zc + ixy) * SB;
+            Unroll<0, Q>::run([&](auto I) {
+                if constexpr (I < NST) d[I] = bF.template decode<I, 0>(ps[I * TL::NT], cd);
+                else d[I] = bF.template loadf<I, 0>(off, cd);
+            });
+        } else {
+            load_pops<S>(bF, (zc + ixy) * SB, cd, d);  // issued early, consumed after the gradient
+        }
         GradAcc<C> acc;
         grad_init(acc);
         C Fv[3], Sv[6];
@@ -600,8 +639,8 @@ template <int S> __device__ __forceinline__ void report_range(float amax, unsign
 #define FUSED_WAVES_PER_EU 2
 #endif
 
-// Occupancy: the LDS (about 130 KB of 160 KB for float) admits one 512-thread work-group per
-// CU, i.e. two waves per SIMD.
+// Occupancy: the LDS (159 KB of 160 KB with the kept populations) admits one 512-thread
+// work-group per CU, i.e. two waves per SIMD.
 template <int S, bool GATHERED, bool HASK, bool THIN1>
 __global__ void __launch_bounds__(TileFor<S>::type::NT) __attribute__((amdgpu_waves_per_eu(FUSED_WAVES_PER_EU)))
 k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
@@ -618,7 +657,8 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
     const int ty = L % fg.tiles_y;
     const int chunk = L / fg.tiles_y;
     float amax = 0.0f;
-    sweep_tile<S, GATHERED, HASK, THIN1>(F, B, Fo, Bo, Tf, Tconst, g, k, cd, fg, tx, ty, chunk, amax);
+    sweep_tile<S, GATHERED, HASK, THIN1, typename TileFor<S>::type, THIN1 ? 0 : fused_stash<S>()>(
+        F, B, Fo, Bo, Tf, Tconst, g, k, cd, fg, tx, ty, chunk, amax);
     report_range<S>(amax, flag);
 }
 
