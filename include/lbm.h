@@ -47,8 +47,8 @@ extern "C" {
 /* Storage precision of the populations and bbar in device memory.  F64 computes in double;
  * the others compute in float.  F16DEV / BF16DEV store 16-bit deviations
  * h = (value - ref) / scale from a reference equilibrium (ref_i = w_i rho_ref for the
- * populations, (T_ref - 1/3) delta for bbar), with one power-of-two scale per stored field,
- * fixed when the fields or the state are set. */
+ * populations, (T_ref - 1/3) delta for bbar), with one power-of-two scale per stored array
+ * (the populations; bbar), fixed when the fields or the state are set. */
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2, LBM_BF16DEV = 3 } lbm_storage;
 
 /* Temperature closure.  THERMAL: T from the total second-moment trace of the bump expansion

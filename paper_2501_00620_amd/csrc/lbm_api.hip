@@ -97,24 +97,31 @@ void codec_defaults(lbm_lattice *h) {
     for (int k = 0; k < NFIELD; k++) h->codec.scale[k] = h->codec.inv[k] = 1.0f;
 }
 
-// Power-of-two scale per field: the largest deviation maps to at most HMAX/1024 (fp16), leaving
-// 1024x headroom for growth before saturation.  The scale only moves binary16's 30-octave
-// window: values stay normal (relative precision 2^-11) down to about 1e-6 of the initial
-// largest deviation, and below that the absolute error is under 1e-9 of it.  A field that
-// starts without deviation gets the scale of a deviation of 1e-3 of its reference magnitude
-// (1e-3 for bbar).  bfloat16 has the
-// exponent range of binary32, so its codes hold the deviations themselves (unit scale).
+// One power-of-two scale per stored array (the 19 populations; the 6 bbar components): the
+// largest deviation in the array maps to at most HMAX/1024 (fp16), leaving 1024x headroom for
+// growth before saturation.  The scale only moves binary16's 30-octave window: values stay
+// normal (relative precision 2^-11) down to about 1e-6 of the array's initial largest
+// deviation, and below that the absolute error is under 1e-9 of it, so per-field scales would
+// buy no precision; one scale per array lets the sweep keep two constants in scalar registers
+// instead of fifty.  A field that starts without deviation counts as a deviation of 1e-3 of its
+// reference magnitude (1e-3 for bbar).  bfloat16 has the exponent range of binary32, so its
+// codes hold the deviations themselves (unit scale).
 void choose_scales(lbm_lattice *h, const double *absmax) {
     if (h->p.storage != LBM_F16DEV) {
         for (int k = 0; k < NFIELD; k++) h->codec.scale[k] = h->codec.inv[k] = 1.0f;
         return;
     }
     const double target = 65504.0 / 1024.0;
+    double mg[2] = {0.0, 0.0};  // populations, bbar
     for (int k = 0; k < NFIELD; k++) {
         double floor_dev = k < Q ? 1e-3 * std::fabs(h->codec.ref[k]) : 1e-3;
         if (floor_dev <= 0) floor_dev = 1e-3;
         const double m = absmax[k] > floor_dev ? absmax[k] : floor_dev;
-        const int e = (int)std::ceil(std::log2(m / target));
+        double &g = mg[k < Q ? 0 : 1];
+        g = m > g ? m : g;
+    }
+    for (int k = 0; k < NFIELD; k++) {
+        const int e = (int)std::ceil(std::log2(mg[k < Q ? 0 : 1] / target));
         const double sc = std::ldexp(1.0, e);
         h->codec.scale[k] = (float)sc;
         h->codec.inv[k] = (float)(1.0 / sc);

@@ -138,12 +138,14 @@ template <int S> struct Buf {
             return __builtin_amdgcn_raw_buffer_load_b16(rs, off, so, 0);
         }
     }
-    // plane K of this array holds codec field F0 + K
+    // plane K of this array holds codec field F0 + K.  A D3Q19 lattice's fp16 codec has one
+    // scale per array (populations from field 0, bbar from field Q), so field F0 stands for the
+    // whole array: two constants stay in scalar registers instead of fifty.
     template <int K, int F0> __device__ __forceinline__ C decode(R v, const Codec &cd) const {
         if constexpr (S == 0 || S == 1) {
             return v;
         } else if constexpr (S == 2) {
-            return cd.scale[F0 + K] * half_bits_to_float(v);
+            return cd.scale[F0] * half_bits_to_float(v);
         } else {  // bf16 codes hold the deviation itself (unit scale)
             return bf16_bits_to_float(v);
         }
@@ -165,7 +167,7 @@ template <int S> struct Buf {
             // evict from L2 the populations the collision reads a second time
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, so, 2);
         } else if constexpr (S == 2) {
-            const float h = v * cd.inv[F0 + K];
+            const float h = v * cd.inv[F0];
             amax = fmaxf(amax, fabsf(h));
             __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)h), rs, off, so, 0);
         } else {
