@@ -125,17 +125,17 @@ template <int S> struct Buf {
     // is kept raw can be issued one plane ahead without the wait for it coming at the load.
     using R = T;
     // plane K of this array: its byte offset in its group goes to the scalar-offset operand
-    // through readfirstlane, so it is known to be wave-uniform.
-    template <int K> __device__ __forceinline__ R loadraw(int off) const {
+    // through readfirstlane, so it is known to be wave-uniform.  POL: cache-policy bits.
+    template <int K, int POL = 0> __device__ __forceinline__ R loadraw(int off) const {
         constexpr int g = K / PPG, j = K % PPG;
         const __amdgpu_buffer_rsrc_t rs = r[g];
         const int so = __builtin_amdgcn_readfirstlane(j * pb);
         if constexpr (S == 0) {
-            return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, so, 0));
+            return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, so, POL));
         } else if constexpr (S == 1) {
-            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, so, 0));
+            return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, so, POL));
         } else {
-            return __builtin_amdgcn_raw_buffer_load_b16(rs, off, so, 0);
+            return __builtin_amdgcn_raw_buffer_load_b16(rs, off, so, POL);
         }
     }
     // plane K of this array holds codec field F0 + K.  A D3Q19 lattice's fp16 codec has one
@@ -504,12 +504,16 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
         C d[Q];
         if constexpr (NST > 0) {
             // the first NST as the source evaluation of this plane left them in LDS, the rest
-            // read again (issued early, consumed after the gradient)
+            // read again (issued early, consumed after the gradient).  It is the last use of
+            // those lines, so in single precision they are read non-temporally, leaving L2 to
+            // the ring and staging reads, which are shared (+1.7%; no measurable effect in 2-byte
+            // storage, which keeps the default policy)
+            constexpr int POL = S == 1 ? 2 : 0;
             const typename Buf<S>::R *ps = pst + ((z - z0) & 1) * NST * TL::NT + threadIdx.x;
             const int off = (zc + ixy) * SB;
             Unroll<0, Q>::run([&](auto I) {
                 if constexpr (I < NST) d[I] = bF.template decode<I, 0>(ps[I * TL::NT], cd);
-                else d[I] = bF.template loadf<I, 0>(off, cd);
+                else d[I] = bF.template decode<I, 0>(bF.template loadraw<I, POL>(off), cd);
             });
         } else {
             load_pops<S>(bF, (zc + ixy) * SB, cd, d);  // issued early, consumed after the gradient

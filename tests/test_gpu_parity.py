@@ -115,11 +115,13 @@ def test_f32_acoustic_pulse_full_grid():
     compare(g, o, 1e-5, "acoustic f32 256^2 step 100")
 
 
-@pytest.mark.parametrize("dims", [(70, 9, 11), (70, 33, 1), (45, 20, 2)])
+@pytest.mark.parametrize("dims", [(70, 9, 11), (70, 33, 1), (45, 20, 2), (70, 9, 37)])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
 def test_fused_equals_two_pass(storage, dims):
     # same arithmetic in a different schedule: equal up to the order of the gradient sums (for
-    # one z plane the fused sweep also regroups the gather and the gradient in-plane)
+    # one z plane the fused sweep also regroups the gather and the gradient in-plane).  nz = 37
+    # runs as two z chunks of 19 planes: a chunk starting at an odd plane, for the populations
+    # the sweep carries in LDS slots chosen by plane parity
     fields = wl.fourier_fields(*dims, seed=12, u_max=0.25)
     out = []
     for kernel in KERNELS:
