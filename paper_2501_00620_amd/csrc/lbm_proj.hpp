@@ -335,7 +335,8 @@ template <int D, int TX_, int TY_> struct ProjTileT {
     // staged bbar* of the previous step: the source grid plus one more ring
     static constexpr int BX = LX + 2, BY = LY + 2 * HY, BN = BX * BY;
 };
-// the one-launch step's tiles (the server uses narrower ones for its small lattices)
+// the one-launch step's tiles; the server's persistent kernel takes the same ones, so that a
+// served lattice steps bitwise as it would alone
 template <int D> using ProjTile = ProjTileT<D, D == 2 ? PROJ2_TX : 256, D == 2 ? PROJ2_TY : 1>;
 
 __device__ __forceinline__ int wrap_mod(int v, int n) {
