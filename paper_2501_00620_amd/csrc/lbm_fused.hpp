@@ -38,17 +38,13 @@ namespace lbm {
 #define GATHER_GROUP 5  // directions per scheduling group in the gather
 #endif
 // Populations of the tile's own sites kept in LDS from the source evaluation to the collision
-// one plane later, per storage (FP32, FP16 deviation, BF16 deviation): the first N of the 19,
-// as many as fit the LDS beside the source and staging planes, or fewer where more measured
-// slower.  The rest are read again at the collision.
+// one plane later, in 4- and 2-byte storage: the first N of the 19, as many as fit the LDS
+// beside the source and staging planes.  The rest are read again at the collision.
 #ifndef FUSED_STASH_F32
 #define FUSED_STASH_F32 8
 #endif
-#ifndef FUSED_STASH_F16
-#define FUSED_STASH_F16 8
-#endif
-#ifndef FUSED_STASH_BF16
-#define FUSED_STASH_BF16 16
+#ifndef FUSED_STASH_16
+#define FUSED_STASH_16 16
 #endif
 
 template <int TX_, int TY_> struct Tile {
@@ -73,9 +69,7 @@ template <int S> struct TileFor { using type = Tile<FUSED_TX, FUSED_TY>; };
 template <> struct TileFor<0> { using type = Tile<64, 2>; };
 // populations kept in LDS by the marching single-lattice kernel (none in double precision, whose
 // LDS is full, and none in the one-plane kernel, which runs several work-groups per CU)
-template <int S> constexpr int fused_stash() {
-    return S == 0 ? 0 : (S == 1 ? FUSED_STASH_F32 : (S == 2 ? FUSED_STASH_F16 : FUSED_STASH_BF16));
-}
+template <int S> constexpr int fused_stash() { return S == 0 ? 0 : (S == 1 ? FUSED_STASH_F32 : FUSED_STASH_16); }
 // Tiles of the one-plane serving kernel.  With one LDS slot of each kind (43 KB) and the in-plane
 // arithmetic it fits 128 VGPRs, so two 512-thread work-groups share a CU (four waves per SIMD),
 // each covering the other's load waits.
