@@ -107,6 +107,8 @@ int lbm_set_state(lbm_handle h, const void *F, const void *b, int on_device);
 
 /* Deviation codec (16-bit storage only): the 25 power-of-two scales and the 25 references
  * (19 populations, then bbar xx yy zz xy xz yz) as doubles.  Decoding is ref + scale * h.
+ * A D3Q19 lattice has one scale for the 19 populations and one for the 6 bbar components
+ * (unit scales for BF16DEV); the entries repeat them per field.
  * Errors: ARG for F64/F32 storage or NULL pointers. */
 int lbm_get_codec(lbm_handle h, double *scales25, double *refs25);
 

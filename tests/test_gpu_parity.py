@@ -192,8 +192,10 @@ def test_deviation_codec_is_bit_exact(storage):
         np.testing.assert_array_equal(Fc[i], enc(o.F[i], refs[i], scales[i]))
     for c in range(6):
         np.testing.assert_array_equal(bc[c], enc(o.b[c], refs[19 + c], scales[19 + c]))
-    # scales are powers of two
+    # scales are powers of two, one per stored array (the populations; bbar): the sweep reads
+    # each array's first entry for all of its planes
     assert np.all(np.log2(scales) == np.round(np.log2(scales)))
+    assert np.all(scales[:19] == scales[0]) and np.all(scales[19:] == scales[19])
 
 
 def test_argument_errors():
