@@ -151,8 +151,9 @@ int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost);
  * with the corrected velocity of Eq. 57, which then carries half of rho a (a Guo-type forcing;
  * the paper drives its Poiseuille and Couette flows with a body force, Sec. III A and C).  In
  * the STANDARD mode the same F and S build the forcing, with u = (j + rho a / 2) / rho.  The
- * field is copied (3 planes of the compute type on the device).  A lattice with a body force
- * steps with the two-pass kernel.  Errors: ARG (dtype, fused kernel forced), OOM, HIP. */
+ * field is copied (3 planes of the compute type on the device).  Both kernels take it: the
+ * fused sweep adds it to the forcing moments of each site before the collision, as the two-pass
+ * collision does.  Errors: ARG (dtype, projected lattice), OOM, HIP. */
 int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device);
 
 /* Walls normal to z (the channels of Sec. III A and C): on = 1 places one wall half-way below

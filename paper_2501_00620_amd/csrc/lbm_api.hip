@@ -274,7 +274,7 @@ template <int S> int step_fused(lbm_lattice *h) {
     const StepConst<C> k = step_const<C>(h);
     int rc = launch_fused<S>((const T *)h->F[h->cur], (const T *)h->B[h->cur], (T *)h->F[1 - h->cur],
                              (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->flag,
-                             h->gathered, h->slots, h->stream);
+                             h->gathered, h->slots, h->stream, (const C *)h->accel);
     if (rc) return fail(LBM_ERR_HIP, "fused launch failed");
     rc = check_launch();
     if (rc) return rc;
@@ -354,9 +354,10 @@ template <int S> int step_std(lbm_lattice *h) {
     return LBM_OK;
 }
 
-// the fused sweep relaxes with a single rate; a lattice with its own ghost rate steps two-pass
+// the fused sweep relaxes with a single rate on a periodic lattice; a lattice with its own ghost
+// rate or with walls steps two-pass
 bool use_fused(const lbm_lattice *h) {
-    return h->kernel != 1 && h->tau_ghost <= 0.0 && !h->accel && !h->walls && fused_supported(geo(h), h->p.storage);
+    return h->kernel != 1 && h->tau_ghost <= 0.0 && !h->walls && fused_supported(geo(h), h->p.storage);
 }
 
 }  // namespace
@@ -409,7 +410,7 @@ int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out) {
         int per_cu = 0;
         (void)dispatch_storage(p->storage, [&](auto SI) -> int {
             constexpr int S = decltype(SI)::value;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<S, false, false, false>,
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<S, false, false, false, false>,
                                                              TileFor<S>::type::NT, 0) != hipSuccess)
                 per_cu = 1;
             return LBM_OK;
@@ -445,7 +446,6 @@ int lbm_set_kernel(lbm_handle h, int kernel) {
         return fail(LBM_ERR_ARG, "fused sweep does not support this lattice shape");
     if (kernel == 2 && h->tau_ghost > 0.0)
         return fail(LBM_ERR_ARG, "the fused sweep relaxes with a single rate (a ghost rate is set)");
-    if (kernel == 2 && h->accel) return fail(LBM_ERR_ARG, "the fused sweep has no body force (one is set)");
     if (kernel == 2 && h->walls) return fail(LBM_ERR_ARG, "the fused sweep is periodic (walls are set)");
     h->kernel = kernel;
     return LBM_OK;
@@ -548,7 +548,6 @@ int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device
     if (!accel) return LBM_OK;
     if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_ARG, "unknown dtype %d", dtype);
     if (h->proj < 3) return fail(LBM_ERR_ARG, "projected lattices have no body force");
-    if (h->kernel == 2) return fail(LBM_ERR_ARG, "the fused sweep has no body force (lbm_set_kernel chose it)");
     const size_t count = 3 * (size_t)h->n, eb = dtype == LBM_DTYPE_F64 ? 8 : 4;
     HIP_TRY(hipMalloc(&h->accel, compute_bytes(h->p.storage) * count));
     void *stage = nullptr;

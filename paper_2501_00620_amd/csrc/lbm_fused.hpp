@@ -15,8 +15,8 @@
 // The algorithmic minimum is 2 x 25 values per lattice update: each site's state read once and
 // written once.  On top of it come the ring sites (neighbouring tiles on the same XCD bring them
 // into L2 at about the same time) and the collision's second read of the tile's populations not
-// kept in LDS (an L2 hit unless the stream in between evicted them).  The staging and source loads are
-// issued one plane iteration ahead of their use.
+// kept in LDS (an L2 hit unless the stream in between evicted them).  The staging and source
+// loads are issued one plane iteration ahead of their use.
 //
 // Work-groups are numbered so that the ones dispatched to one XCD (block index mod 8) take
 // neighbouring tiles of the same z chunk, which share their rings through that XCD's L2.
@@ -285,8 +285,10 @@ __device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typen
 // part of rho b enters the second-moment source).  THIN1: the lattice has exactly one z plane
 // (one LDS slot of each kind, about a third of the LDS, so that several work-groups share a CU).
 // amax collects |16-bit codes| stored.  NST_: populations of the tile's own sites carried in
-// LDS from the source evaluation to the collision (staged kernels only).
-template <int S, bool GATHERED, bool HASK, bool THIN1 = false, typename TL = typename TileFor<S>::type, int NST_ = 0>
+// LDS from the source evaluation to the collision (staged kernels only).  FORCE: a body-force
+// acceleration field `accel` (3 planes of n) enters the forcing moments before the collision.
+template <int S, bool GATHERED, bool HASK, bool THIN1 = false, typename TL = typename TileFor<S>::type, int NST_ = 0,
+          bool FORCE = false>
 __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restrict__ F,
                                            const typename Storage<S>::T *__restrict__ B,
                                            typename Storage<S>::T *__restrict__ Fo,
@@ -294,7 +296,8 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
                                            const typename Storage<S>::C *__restrict__ Tf,
                                            typename Storage<S>::C Tconst, const Geo &g,
                                            const StepConst<typename Storage<S>::C> &k, const Codec &cd,
-                                           const FusedGeo &fg, int tx, int ty, int chunk, float &amax) {
+                                           const FusedGeo &fg, int tx, int ty, int chunk, float &amax,
+                                           const typename Storage<S>::C *__restrict__ accel = nullptr) {
     using C = typename Storage<S>::C;
     using T = typename Storage<S>::T;
     constexpr int TX = TL::TX, TY = TL::TY, NS = TL::NS, NB2 = TL::NB2;
@@ -546,6 +549,11 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
             grad_finish(acc, Fv, Sv);
         }
         const PopMoments<C> m = pop_moments(d, k.rho_ref);
+        if constexpr (FORCE) {
+            const int s = zc + ixy;
+            const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
+            add_body_force(m, a, Fv, Sv);
+        }
         collide(d, cur.beta, m, Fv, Sv, cur.theta, k);
         int Zo[3];
         Zo[0] = (wz == 0 ? g.nz - 1 : wz - 1) * nxy;
@@ -640,13 +648,14 @@ template <int S> __device__ __forceinline__ void report_range(float amax, unsign
 #endif
 
 // Occupancy: the LDS (159 KB of 160 KB with the kept populations) admits one 512-thread
-// work-group per CU, i.e. two waves per SIMD.
-template <int S, bool GATHERED, bool HASK, bool THIN1>
+// work-group per CU, i.e. two waves per SIMD.  FORCE: with a body-force field (accel).
+template <int S, bool GATHERED, bool HASK, bool THIN1, bool FORCE>
 __global__ void __launch_bounds__(TileFor<S>::type::NT) __attribute__((amdgpu_waves_per_eu(FUSED_WAVES_PER_EU)))
 k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
         typename Storage<S>::T *__restrict__ Fo, typename Storage<S>::T *__restrict__ Bo,
         const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
-        StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag, FusedGeo fg) {
+        StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag, FusedGeo fg,
+        const typename Storage<S>::C *__restrict__ accel) {
     // XCD-aware work-group numbering: the work-groups of one XCD (block index mod 8) take
     // neighbouring tiles of the same z chunk
     const int nblk = gridDim.x;
@@ -657,8 +666,8 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
     const int ty = L % fg.tiles_y;
     const int chunk = L / fg.tiles_y;
     float amax = 0.0f;
-    sweep_tile<S, GATHERED, HASK, THIN1, typename TileFor<S>::type, THIN1 ? 0 : fused_stash<S>()>(
-        F, B, Fo, Bo, Tf, Tconst, g, k, cd, fg, tx, ty, chunk, amax);
+    sweep_tile<S, GATHERED, HASK, THIN1, typename TileFor<S>::type, THIN1 ? 0 : fused_stash<S>(), FORCE>(
+        F, B, Fo, Bo, Tf, Tconst, g, k, cd, fg, tx, ty, chunk, amax, accel);
     report_range<S>(amax, flag);
 }
 
@@ -717,7 +726,7 @@ template <int S>
 int launch_fused(const typename Storage<S>::T *F, const typename Storage<S>::T *B, typename Storage<S>::T *Fo,
                  typename Storage<S>::T *Bo, const typename Storage<S>::C *Tf, typename Storage<S>::C Tconst,
                  const Geo &g, const StepConst<typename Storage<S>::C> &k, const Codec &cd, unsigned *flag,
-                 bool gathered, int slots, hipStream_t stream) {
+                 bool gathered, int slots, hipStream_t stream, const typename Storage<S>::C *accel = nullptr) {
     using TL = typename TileFor<S>::type;
     const FusedGeo fg = fused_geometry<S>(g, slots);
     const long long blocks = (long long)fg.tiles_x * fg.tiles_y * fg.nchunks;
@@ -727,8 +736,12 @@ int launch_fused(const typename Storage<S>::T *F, const typename Storage<S>::T *
     // one z plane: the instantiation with the in-plane gather and gradient (the serving kernel
     // sweeps such lattices with the same arithmetic)
     auto go = [&](auto G, auto H, auto T1) {
-        hipLaunchKernelGGL((k_fused<S, decltype(G)::value, decltype(H)::value, decltype(T1)::value>), grid, block, 0,
-                           stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg);
+        if (accel)
+            hipLaunchKernelGGL((k_fused<S, decltype(G)::value, decltype(H)::value, decltype(T1)::value, true>), grid,
+                               block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg, accel);
+        else
+            hipLaunchKernelGGL((k_fused<S, decltype(G)::value, decltype(H)::value, decltype(T1)::value, false>), grid,
+                               block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg, accel);
     };
     using tt = std::true_type;
     using ff = std::false_type;

@@ -170,7 +170,7 @@ class Lattice:
 
     def set_body_force(self, accel):
         """Body-force acceleration: an array (3, nz, ny, nx), a 3-vector (uniform), or None to
-        remove it.  Such a lattice steps with the two-pass kernel."""
+        remove it.  Both the fused and the two-pass step take it."""
         if accel is None:
             _check(_lib.lbm_set_body_force(self._h, None, 0, 0))
             return

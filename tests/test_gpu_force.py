@@ -30,14 +30,16 @@ def force_field(dims, seed, amp=2e-4):
     return amp * a
 
 
+@pytest.mark.parametrize("kernel", ["auto", "two_pass"])
 @pytest.mark.parametrize("dims", [(17, 9, 5), (32, 16, 1), (8, 6, 7)])
 @pytest.mark.parametrize("mode", ["thermal", "iso", "standard"])
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
-def test_body_force_parity(dims, mode, storage, tol):
+def test_body_force_parity(dims, mode, storage, tol, kernel):
+    # kernel "auto" steps a periodic lattice with the fused sweep (STANDARD: its own kernel)
     tau, steps = 0.7, 30
     fields = wl.fourier_fields(*dims, seed=23, u_max=0.2)
     accel = force_field(dims, 24)
-    g = lbm().Lattice(*dims, tau, storage=storage, mode=mode)
+    g = lbm().Lattice(*dims, tau, storage=storage, mode=mode, kernel=kernel)
     g.set_fields(*fields)
     g.set_body_force(accel)
     o = oracle.OracleLattice(*dims, tau, mode=mode)
@@ -96,8 +98,41 @@ def test_removing_the_force_restores_the_fused_step():
     np.testing.assert_array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("dims", [(70, 9, 11), (70, 33, 1), (45, 20, 2), (70, 9, 37)])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev", "bf16dev"])
+def test_fused_equals_two_pass_with_force(storage, dims):
+    # the fused sweep adds the force where the two-pass collision does: equal up to the order of
+    # the gradient sums, as without a force
+    fields = wl.fourier_fields(*dims, seed=12, u_max=0.25)
+    accel = force_field(dims, 13)
+    out = []
+    for kernel in ("fused", "two_pass"):
+        g = lbm().Lattice(*dims, 0.65, storage=storage, kernel=kernel)
+        g.set_fields(*fields)
+        g.set_body_force(accel)
+        g.step(7)
+        F, b = g.get_state()
+        out.append((F.cpu().numpy(), b.cpu().numpy()))
+    tol = {"f64": 1e-14, "f32": 1e-6, "f16dev": 1e-3, "bf16dev": 1e-2}[storage]
+    assert rel_l2(out[0][0], out[1][0]) <= tol
+    assert rel_l2(out[0][1], out[1][1]) <= tol
+    # and the force changes the result by far more than the bar (the comparison is not vacuous;
+    # over 7 steps the force moves the state by ~1e-4, under the 16-bit bars, so checked where
+    # the bar is tight)
+    if storage in ("f64", "f32"):
+        g = lbm().Lattice(*dims, 0.65, storage=storage, kernel="fused")
+        g.set_fields(*fields)
+        g.step(7)
+        assert rel_l2(g.get_state()[0].cpu().numpy(), out[0][0]) > 10 * tol
+
+
 def test_body_force_argument_errors():
     L = lbm()
-    g = L.Lattice(8, 8, 8, 0.7, storage="f32", kernel="fused")
+    g = L.Lattice(8, 8, 1, 0.7, storage="f32")
+    g.set_projection(2)
     with pytest.raises(L.LBMError):
         g.set_body_force([1e-4, 0, 0])
+    # the fused sweep takes a force, and a force does not prevent choosing it
+    g = L.Lattice(8, 8, 8, 0.7, storage="f32", kernel="fused")
+    g.set_body_force([1e-4, 0, 0])
+    g.set_kernel("fused")
