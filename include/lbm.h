@@ -135,7 +135,11 @@ int lbm_invariants(lbm_handle h, double out[5]);
 int lbm_health(lbm_handle h, long counts[2], double *max_u);
 
 /* Per-step launch configuration. kernel: 0 = auto, 1 = two-pass (predictor sources to a
- * buffer, then gradient + collision), 2 = fused z-marching sweep with LDS planes of sources. */
+ * buffer, then gradient + collision), 2 = fused z-marching sweep with LDS planes of sources.
+ * Auto takes the fused sweep for a periodic lattice (with or without a body force) whose buffers
+ * fit its 32-bit offsets, and the two-pass step for walls or a ghost rate.  Errors: ARG (bad
+ * choice; the fused sweep on a projected lattice, on walls, with a ghost rate, or beyond its
+ * offsets). */
 int lbm_set_kernel(lbm_handle h, int kernel);
 
 /* Relaxation time of the nine non-hydrodynamic moments, rows 11-19 of Table I (Appendix B):
