@@ -46,6 +46,9 @@ namespace lbm {
 #ifndef FUSED_STASH_16
 #define FUSED_STASH_16 16
 #endif
+#ifndef FUSED_STASH_F64
+#define FUSED_STASH_F64 0
+#endif
 
 template <int TX_, int TY_> struct Tile {
     static constexpr int TX = TX_, TY = TY_;
@@ -58,7 +61,9 @@ template <int TX_, int TY_> struct Tile {
 };
 
 // 4- and 2-byte storage compute in float: 64 x 8 tiles (71 KB of sources + 59 KB of staged
-// bbar*); double needs twice the bytes, so 64 x 2.
+// bbar*).  Double needs twice the bytes per site: 32 x 8 tiles (73 + 62 KB), 256 threads, so
+// that the one work-group the LDS admits per CU still gives each SIMD a wave (64 x 2 tiles left
+// two SIMDs idle and recomputed a ring larger than the tile: 2.3x slower).
 #ifndef FUSED_TX
 #define FUSED_TX 64
 #endif
@@ -66,10 +71,18 @@ template <int TX_, int TY_> struct Tile {
 #define FUSED_TY 8
 #endif
 template <int S> struct TileFor { using type = Tile<FUSED_TX, FUSED_TY>; };
-template <> struct TileFor<0> { using type = Tile<64, 2>; };
-// populations kept in LDS by the marching single-lattice kernel (none in double precision, whose
-// LDS is full, and none in the one-plane kernel, which runs several work-groups per CU)
-template <int S> constexpr int fused_stash() { return S == 0 ? 0 : (S == 1 ? FUSED_STASH_F32 : FUSED_STASH_16); }
+#ifndef FUSED64_TX
+#define FUSED64_TX 32
+#endif
+#ifndef FUSED64_TY
+#define FUSED64_TY 8
+#endif
+template <> struct TileFor<0> { using type = Tile<FUSED64_TX, FUSED64_TY>; };
+// populations kept in LDS by the marching single-lattice kernel (none in the one-plane kernel,
+// which runs several work-groups per CU)
+template <int S> constexpr int fused_stash() {
+    return S == 0 ? FUSED_STASH_F64 : (S == 1 ? FUSED_STASH_F32 : FUSED_STASH_16);
+}
 // Tiles of the one-plane serving kernel.  With one LDS slot of each kind (43 KB) and the in-plane
 // arithmetic it fits 128 VGPRs, so two 512-thread work-groups share a CU (four waves per SIMD),
 // each covering the other's load waits.
