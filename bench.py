@@ -2,8 +2,9 @@
 
 Timed workload (one "step" = one full pass of the sweep over the lattice): the 3-D compressible
 Taylor-Green vortex on a 256^3 periodic D3Q19 lattice, Mach 0.5, tau = 0.55, FP32 storage and
-arithmetic, inputs resident in HBM.  W untimed warm-up steps, then K steps between HIP events
-recorded on the lattice's stream (barrier + synchronize on both sides).
+arithmetic, inputs resident in HBM.  W untimed warm-up steps, then exactly K timed steps in five
+consecutive windows, each between HIP events recorded on the lattice's stream (synchronize on
+both sides); the headline is the median window's rate.
 
 Also reported on the same JSON line:
   roofline      algorithmic bytes per step (2 x 25 values x 4 B per site) over the measured
@@ -31,8 +32,9 @@ Also reported on the same JSON line:
                 throughput; Kolmogorov-flow amplitude against A / (T tau k^2)), and the walls
                 (two-pass channel throughput; the gravity Couette flow of Sec. III C in two
                 frames, bump vs standard, against its closed form);
-  cpu_baseline  the FP64 CPU oracle timed on this host's cores on a bounded sample (a 48^3
-                Taylor-Green vortex for ~10 s).
+  cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample (a 48^3 Taylor-Green
+                vortex for ~10 s) with OpenMP on all allowed threads, and again on one core;
+                the CPU model.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
 """
@@ -74,6 +76,28 @@ def traffic_from_profiles(kernel, workload, launch_sites):
     if rec.get("source_hash") != source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def timed_windows(lat, steps, warmup, windows=5):
+    """W warm-up steps, then exactly `steps` timed steps split into `windows` consecutive
+    windows, each between HIP events on the lattice's stream.  Returns the per-step seconds of
+    each window."""
+    import torch
+    lat.step(warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    windows = max(1, min(windows, steps))
+    sizes = [steps // windows] * windows
+    sizes[-1] += steps - sum(sizes)
+    stream = lat.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(windows + 1)]
+    ev[0].record(stream)
+    for w, k in enumerate(sizes):
+        lat.step(k)
+        ev[w + 1].record(stream)
+    ev[-1].synchronize()
+    torch.cuda.synchronize()
+    return [ev[w].elapsed_time(ev[w + 1]) / 1e3 / k for w, k in enumerate(sizes)]
 
 
 def timed_steps(lat, steps, warmup):
@@ -131,16 +155,6 @@ def run_variants(n, steps, tau, mach, every=500):
     return out
 
 
-def serving_requests(n_requests, rate, seed):
-    """Arrival times, grid edges and field seeds of the served batch (fixed by `seed`)."""
-    import numpy as np
-    rng = np.random.Generator(np.random.PCG64(seed))
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
-    sizes = rng.integers(64, 513, size=n_requests)
-    field_seeds = rng.integers(0, 1 << 62, size=n_requests)
-    return arrivals, sizes, field_seeds
-
-
 def run_serving(storage, n_requests=512, rate=50.0, steps=2000, budget=4 << 30, bundle=50, seed=2024, tau=0.8):
     """Served batch: independent n x n x 1 four-quadrant Riemann problems, n uniform in
     [64, 512], Poisson arrivals at `rate` per second, admitted by a device-memory budget.
@@ -148,14 +162,14 @@ def run_serving(storage, n_requests=512, rate=50.0, steps=2000, budget=4 << 30, 
     outcomes (latency, or the reason a request failed)."""
     import numpy as np
     from paper_2501_00620_amd import lbm, workloads
-    arrivals, sizes, field_seeds = serving_requests(n_requests, rate, seed)
+    arrivals, sizes, field_seeds = workloads.served_batch(n_requests, rate, seed)
     ids = []
     with lbm.Server(budget_bytes=budget, bundle_steps=bundle, storage=storage, health_every=10) as srv:
         t0 = time.perf_counter()
         for k in range(n_requests):
             while time.perf_counter() - t0 < arrivals[k]:
                 time.sleep(min(0.002, max(0.0, arrivals[k] - (time.perf_counter() - t0))))
-            f = workloads.riemann2d_request(np.random.Generator(np.random.PCG64(int(field_seeds[k]))), n=int(sizes[k]))
+            f = workloads.served_request(sizes[k], field_seeds[k])
             ids.append(srv.submit(*f, tau=tau, steps=steps))
         status = [srv.wait(r, timeout=600) for r in ids]
         times = np.array([srv.poll(r)[1:] for r in ids])
@@ -497,10 +511,11 @@ def galilean_contrast(U=0.2, N=64, T0=1.0 / 3.0, tau=0.6, steps=2000, every=50):
     return out
 
 
-def cpu_baseline(seconds=10.0, n=48, mach=0.5, tau=0.55):
+def oracle_rate(seconds, n=48, mach=0.5, tau=0.55):
+    """MLUPS of the FP64 CPU oracle as it stands on a Taylor-Green vortex n^3, stepping for about
+    `seconds` (OpenMP threads from OMP_NUM_THREADS).  Returns (mlups, steps, seconds)."""
     import oracle
     from paper_2501_00620_amd import workloads
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rho, u, T = workloads.taylor_green(n, mach=mach)
     o = oracle.OracleLattice(n, n, n, tau)
     o.init(rho, u, T)
@@ -508,12 +523,39 @@ def cpu_baseline(seconds=10.0, n=48, mach=0.5, tau=0.55):
     t0 = time.perf_counter()
     steps = 0
     while time.perf_counter() - t0 < seconds:
-        o.step(2)
-        steps += 2
+        o.step(1)
+        steps += 1
     dt = time.perf_counter() - t0
-    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+    return n ** 3 * steps / dt / 1e6, steps, dt
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seconds=10.0, n=48, mach=0.5, tau=0.55):
+    """The oracle timed on this host: with OpenMP on all the threads OMP_NUM_THREADS allows
+    (the reported value), and on one core in a child process (OMP_NUM_THREADS=1)."""
+    import subprocess
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    mlups, steps, dt = oracle_rate(seconds, n, mach, tau)
+    child = subprocess.run(
+        [sys.executable, "-c", f"import json, bench; print(json.dumps(bench.oracle_rate({seconds}, {n}, {mach}, {tau})))"],
+        cwd=ROOT, env={**os.environ, "OMP_NUM_THREADS": "1"}, capture_output=True, text=True)
+    one = json.loads(child.stdout.strip().splitlines()[-1]) if child.returncode == 0 else None
+    return {"value": round(mlups, 2), "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"Taylor-Green vortex {n}^3, Mach {mach}, tau {tau}, FP64, {steps} steps "
-                      f"({dt:.1f} s) on {threads} OpenMP threads"}
+                      f"({dt:.1f} s) on {threads} OpenMP threads",
+            "single_core": None if one is None else {
+                "value": round(one[0], 3), "unit": "MLUPS", "cores": 1,
+                "sample": f"the same lattice, {one[1]} steps ({one[2]:.1f} s) on 1 thread"},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def copy_ceiling(nbytes=1 << 30, reps=10):
@@ -570,6 +612,7 @@ def main():
               "(domain decomposition is design-only); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
@@ -586,28 +629,33 @@ def main():
         print(json.dumps({"projections": projections()}))
         return
     n, tau, mach = args.n, 0.55, 0.5
+    # the copy ceiling first: it also brings the device out of idle before the timed steps
+    copy_gbs = copy_ceiling()
     rho, u, T = workloads.taylor_green(n, mach=mach)
     lat = lbm.Lattice(n, n, n, tau, storage=args.storage, kernel=args.kernel)
     lat.set_fields(rho, u, T)
     torch.cuda.synchronize()
-    secs = timed_steps(lat, args.steps, args.warmup)
-    print(f"[bench] timed {args.steps} steps: {secs * 1e3 / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    per_step = timed_windows(lat, args.steps, args.warmup)
+    secs_step = float(np.median(per_step))
+    print(f"[bench] timed {args.steps} steps in {len(per_step)} windows: median {secs_step * 1e3:.3f} ms/step "
+          f"({', '.join(f'{t * 1e3:.3f}' for t in per_step)})", file=sys.stderr, flush=True)
     health = lat.health()
     sites = n ** 3
-    ms_per_step = secs * 1e3 / args.steps
-    mlups = sites * args.steps / secs / 1e6
+    ms_per_step = secs_step * 1e3
+    mlups = sites / secs_step / 1e6
     bytes_per_step = sites * VALUES_PER_LUP * BYTES_PER_VALUE[args.storage]
-    achieved = bytes_per_step / (secs / args.steps) / 1e9
+    achieved = bytes_per_step / secs_step / 1e9
     kname = "k_fused" if args.kernel in ("auto", "fused") else "k_two_pass"
     workload = f"tgv{n}_{args.storage}"
     traffic = traffic_from_profiles(kname, workload, sites)
     del lat
     torch.cuda.empty_cache()
-    copy_gbs = copy_ceiling()
 
     line = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "timing": {"windows": len(per_step), "ms_per_step_each": [round(t * 1e3, 4) for t in per_step],
+                   "statistic": "median over consecutive windows of the K timed steps"},
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.storage == "f32" else args.storage,
         "data": "synthetic (seeded Taylor-Green vortex initial fields)",
         "config": {"workload": f"3-D compressible Taylor-Green vortex {n}^3 periodic D3Q19, Mach {mach}, "

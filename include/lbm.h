@@ -40,7 +40,7 @@ extern "C" {
 #define LBM_ERR_OOM (-2)      /* device allocation failed                                    */
 #define LBM_ERR_HIP (-3)      /* HIP runtime error; message carries the runtime's string     */
 #define LBM_ERR_DIVERGED (-4) /* non-finite value or rho <= 0 found by a health check        */
-#define LBM_ERR_RANGE (-5)    /* 16-bit deviation encode saturated (value clamped)          */
+#define LBM_ERR_RANGE (-5)    /* a 16-bit deviation code overflowed (stored as +-inf)       */
 #define LBM_ERR_BUSY (-6)     /* server: request queued, not admitted yet (not a failure)   */
 #define LBM_ERR_STATE (-7)    /* call out of order (e.g. step before set_fields)            */
 
@@ -48,7 +48,10 @@ extern "C" {
  * the others compute in float.  F16DEV / BF16DEV store 16-bit deviations
  * h = (value - ref) / scale from a reference equilibrium (ref_i = w_i rho_ref for the
  * populations, (T_ref - 1/3) delta for bbar), with one power-of-two scale per stored array
- * (the populations; bbar), fixed when the fields or the state are set. */
+ * (the populations; bbar), fixed when the fields or the state are set.  Every kernel encodes
+ * with round-to-nearest-even; a value whose code would exceed the largest finite one is stored
+ * as +-inf (never clamped) and sets the lattice's range flag, which lbm_set_fields,
+ * lbm_set_state and lbm_health report as LBM_ERR_RANGE (and clear). */
 typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2, LBM_BF16DEV = 3 } lbm_storage;
 
 /* Temperature closure.  THERMAL: T from the total second-moment trace of the bump expansion
@@ -84,7 +87,7 @@ int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out);
  * reference).  rho: n values, u: 3n, T: n, all of `dtype`.  In ISO and STANDARD mode T is also
  * kept as the prescribed temperature field.  For 16-bit storage the codec scales are
  * chosen here from the initial deviations.  Errors: ARG (rho <= 0 or non-finite anywhere),
- * RANGE, HIP. */
+ * RANGE (an initial value overflowed its code), HIP. */
 int lbm_set_fields(lbm_handle h, const void *rho, const void *u, const void *T, int dtype,
                    int on_device);
 
@@ -101,7 +104,10 @@ int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on
 /* Checkpoint / parity: the post-stream state (fbar: 19n doubles, bbar: 6n doubles; on a projected
  * lattice the nf and nb planes of lbm_get_projection, get only), decoded to double.
  * lbm_set_state loads such a state (re-encoding it; codec scales are re-chosen for 16-bit
- * storage).  get then set then step is bit-identical to stepping on for F64 and F32. */
+ * storage).  get then set then step continues the run: the checkpoint holds bbar gathered, which
+ * the uninterrupted run gathers inside its next step in another order of summation, so the two
+ * agree to the rounding of that sum (about 1e-16 relative in F64, 1e-7 in F32), not bit for bit.
+ * Two runs from the same state are bit-identical. */
 int lbm_get_state(lbm_handle h, void *F, void *b, int on_device);
 int lbm_set_state(lbm_handle h, const void *F, const void *b, int on_device);
 
@@ -131,7 +137,9 @@ int lbm_get_stored(lbm_handle h, void *F, void *b, int *b_is_gathered, int on_de
 int lbm_invariants(lbm_handle h, double out[5]);
 
 /* Health check: counts of sites with a non-finite stored value and with rho <= 0, and the
- * largest |u*| (uncorrected velocity).  Returns LBM_ERR_DIVERGED if either count is nonzero. */
+ * largest |u*| (uncorrected velocity).  counts and max_u are filled in whatever the result.
+ * Returns LBM_ERR_RANGE if a 16-bit code overflowed since the state was set or last checked
+ * (the flag is then cleared), else LBM_ERR_DIVERGED if either count is nonzero. */
 int lbm_health(lbm_handle h, long counts[2], double *max_u);
 
 /* Per-step launch configuration. kernel: 0 = auto, 1 = two-pass (predictor sources to a

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 
 #include "../../include/lbm.h"
@@ -66,25 +67,6 @@ int blocks_for(int n) { return (n + BLOCK - 1) / BLOCK; }
 int red_blocks(int n) {
     int b = blocks_for(n);
     return b < RED_MAX_BLOCKS ? b : RED_MAX_BLOCKS;
-}
-
-template <typename C> StepConst<C> step_const(const lbm_lattice *h) {
-    StepConst<C> k;
-    const double omega = 1.0 / (h->p.tau + 0.5);
-    k.omega = (C)omega;
-    k.half_omega = (C)(0.5 * omega);
-    k.fcoef = (C)(1.0 - 0.5 * omega);
-    k.rho_ref = (C)h->p.rho_ref;
-    k.theta_ref = (C)(h->p.T_ref - 1.0 / 3.0);
-    k.K = (C)(h->p.rho_ref * (h->p.T_ref - 1.0 / 3.0));
-    k.om1 = (C)(1.0 - omega);
-    k.ghost = h->tau_ghost > 0.0 ? (C)(1.0 - (1.0 / (h->tau_ghost + 0.5)) / omega) : C(0);
-    for (int c = 0; c < 3; c++) {
-        k.uwb[c] = (C)h->uw[c];
-        k.uwt[c] = (C)h->uw[3 + c];
-    }
-    k.iso = h->p.mode == LBM_ISO;
-    return k;
 }
 
 // Codec references: ref_i = w_i rho_ref, bbar_ref = (T_ref - 1/3) I; unit scales until chosen.
@@ -180,7 +162,6 @@ template <typename Fn> int dispatch_proj(const lbm_lattice *h, Fn &&fn) {
     using D1 = std::integral_constant<int, 1>;
     const bool th = h->p.mode == LBM_THERMAL;
     return dispatch_storage(h->p.storage, [&](auto SI) -> int {
-        constexpr int S = decltype(SI)::value;
         if (h->proj == 2)
             return th ? fn(SI, D2{}, std::true_type{}) : fn(SI, D2{}, std::false_type{});
         return th ? fn(SI, D1{}, std::true_type{}) : fn(SI, D1{}, std::false_type{});
@@ -200,6 +181,11 @@ template <bool MAX> int finish_reduction(lbm_lattice *h, int nblocks, int K, dou
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(host, h->red_out, sizeof(double) * K, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int clear_flag(lbm_lattice *h) {
+    HIP_TRY(hipMemsetAsync(h->flag, 0, sizeof(unsigned), h->stream));
     return LBM_OK;
 }
 
@@ -633,6 +619,11 @@ int lbm_set_fields(lbm_handle h, const void *rho, const void *u, const void *T, 
     const int rb = red_blocks(h->n);
     double absmax[NFIELD + 1];
     codec_defaults(h);
+    // a range flag left by steps of the previous state is not this state's
+    if (int e = clear_flag(h)) {
+        if (stage) (void)hipFree(stage);
+        return e;
+    }
     if (dtype == LBM_DTYPE_F64)
         hipLaunchKernelGGL(k_absmax_fields<double>, dim3(rb), dim3(BLOCK), 0, h->stream, (const double *)dr,
                            (const double *)du, (const double *)dT, g, h->p.rho_ref, h->p.T_ref, h->partial);
@@ -966,6 +957,10 @@ int lbm_set_state(lbm_handle h, const void *F, const void *b, int on_device) {
     const int rb = red_blocks(h->n);
     double absmax[NFIELD + 1];
     codec_defaults(h);
+    if (int e = clear_flag(h)) {
+        if (stage) (void)hipFree(stage);
+        return e;
+    }
     hipLaunchKernelGGL(k_absmax_state<0>, dim3(rb), dim3(BLOCK), 0, h->stream, dF, dB, g, h->codec, h->partial);
     int rc = check_launch();
     if (!rc) rc = finish_reduction<true>(h, rb, NFIELD + 1, absmax);
@@ -1082,12 +1077,18 @@ int lbm_health(lbm_handle h, long counts[2], double *max_u) {
             if (e != hipSuccess) rc = fail(LBM_ERR_HIP, "health: %s", hipGetErrorString(e));
         }
     }
+    // the range flag of 16-bit codes that overflowed since the state was set or last checked
+    unsigned range = 0;
+    if (!rc) rc = read_clear_flag(h, &range);
     if (rc) return rc;
     if (counts) {
         counts[0] = (long)sums[0];
         counts[1] = (long)sums[1];
     }
     if (max_u) *max_u = mx;
+    if (range & 1u)
+        return fail(LBM_ERR_RANGE, "16-bit code overflow since the last check (stored as +-inf); %ld non-finite sites, "
+                    "%ld sites with rho <= 0", (long)sums[0], (long)sums[1]);
     if (sums[0] > 0 || sums[1] > 0) return fail(LBM_ERR_DIVERGED, "%ld non-finite sites, %ld sites with rho <= 0", (long)sums[0], (long)sums[1]);
     return LBM_OK;
 }

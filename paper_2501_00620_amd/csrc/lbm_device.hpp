@@ -73,29 +73,26 @@ template <> struct Storage<1> {
 __device__ __forceinline__ float half_bits_to_float(uint16_t b) {
     return (float)__builtin_bit_cast(_Float16, b);
 }
-// float -> fp16 code, round to nearest even; |h| > 65504 saturates and sets the flag, NaN is
-// kept (and flagged) so that a health check still sees it.
+// Overflow of a 16-bit code.  Conversion rounds to nearest even, so a finite value turns into
+// +-inf exactly when its magnitude reaches the midpoint between the largest finite code and the
+// next power of two: 65520 for fp16, (2 - 2^-8) 2^127 for bf16.  Such a value is stored as +-inf
+// (nothing is clamped) and sets the range flag; a NaN is stored as NaN without the flag, since
+// it comes only from a state that is already non-finite, which the health check counts.
+constexpr float HALF_OVERFLOW = 65520.0f;
+__device__ __forceinline__ float bf16_overflow() { return __uint_as_float(0x7f7f8000u); }
+
+// float -> fp16 code, round to nearest even (hardware conversion).
 __device__ __forceinline__ uint16_t float_to_half_bits(float h, unsigned &sat) {
-    if (h != h) {
-        sat = 1u;
-        return (uint16_t)0x7e00u;
-    }
-    if (!(fabsf(h) <= 65504.0f)) {
-        sat = 1u;
-        h = h > 0.0f ? 65504.0f : -65504.0f;
-    }
+    if (fabsf(h) >= HALF_OVERFLOW) sat = 1u;
     return __builtin_bit_cast(uint16_t, (_Float16)h);
 }
 __device__ __forceinline__ float bf16_bits_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 // float -> bf16 code, round to nearest even on the dropped 16 bits; NaN stays NaN.
 __device__ __forceinline__ uint16_t float_to_bf16_bits(float h, unsigned &sat) {
     uint32_t u = __float_as_uint(h);
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-        sat = 1u;
-        return (uint16_t)0x7fc0u;
-    }
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0u;
+    if (fabsf(h) >= bf16_overflow()) sat = 1u;
     u += 0x7fffu + ((u >> 16) & 1u);
-    if ((u & 0x7f800000u) == 0x7f800000u) sat = 1u;  // rounded to infinity
     return (uint16_t)(u >> 16);
 }
 
@@ -199,10 +196,14 @@ __device__ __forceinline__ void variance_eq_dev(C ux, C uy, C uz, C theta, C b[N
     b[5] = uy * uz * third;
 }
 
-// 1/x: the hardware reciprocal in single precision (within about 1 ulp; the single-precision
-// path is held to a relative error of 1e-5), correctly rounded division in double.
+// 1/x.  Single precision: the hardware reciprocal (about 1 ulp, and not unbiased) refined by one
+// Newton-Raphson step r' = r + r (1 - x r), which leaves an error of about half an ulp; double:
+// correctly rounded division.
 template <typename C> __device__ __forceinline__ C recip(C x) { return C(1) / x; }
-template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ float recip<float>(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
 
 // Moments of the deviation populations.
 template <typename C> struct PopMoments {
@@ -385,10 +386,10 @@ __device__ __forceinline__ void add_body_force(const PopMoments<C> &m, const C a
 // the odd part M of c:  c_i = P + M,  c_i' = P - M.  Per pair (axis a, or plane (a,b) with
 // q = s_a u_a + s_b u_b):
 //   faces:  P = omega [drho/18 + rho/18 (2 u_a^2 - 2 o_a + 6 u_a^2 o_a)] + (fcoef/4)(S_aa - trS/3)
-//           M = omega rho u_a / 6 + (fcoef/6) F_a
+//           M = omega rho u_a / 6 + (fcoef/6) F_a  = G_a / 6,  G = omega j + F
 //   edges:  P = omega [drho/36 - rho/36 (u_a^2 + u_b^2 + 6 u_a^2 u_b^2) + rho q^2 / 12]
 //               + (fcoef/8)(S_aa + S_bb - trS/3) + s_a s_b (fcoef/4) S_ab
-//           M = omega rho q / 12 + (fcoef/12)(s_a F_a + s_b F_b)
+//           M = omega rho q / 12 + (fcoef/12)(s_a F_a + s_b F_b)  = (s_a G_a + s_b G_b) / 12
 //   rest:   c = omega [drho/3 - rho/9 (2|u|^2 + 6(ux^2 uy^2 + ux^2 uz^2 + uy^2 uz^2))] - fcoef trS/2
 // (the grouped Appendix A equilibrium and the Hermite-form forcing written above).
 template <typename C>
@@ -427,10 +428,18 @@ __device__ __forceinline__ void collide(C d[Q], C beta[NB], const PopMoments<C> 
     const C om = k.omega, om1 = k.om1, fc = k.fcoef;
     const C wr = om * m.rho, wd = om * m.drho;
     const C wr9 = wr * C(1.0 / 9.0), wr18 = wr * C(1.0 / 18.0), wr36 = wr * C(1.0 / 36.0);
-    const C wr12 = wr * C(1.0 / 12.0), wr6 = wr * C(1.0 / 6.0);
+    const C wr12 = wr * C(1.0 / 12.0);
     const C wd18 = wd * C(1.0 / 18.0), wd36 = wd * C(1.0 / 36.0);
     const C t3 = trS * third;
-    const C fc4 = fc * C(0.25), fc6 = fc * C(1.0 / 6.0), fc8 = fc * C(0.125), fc12 = fc * C(1.0 / 12.0);
+    const C fc4 = fc * C(0.25), fc8 = fc * C(0.125);
+    // Odd parts.  The momentum the update hands out is G = omega rho u + (1 - omega/2) F
+    // = omega j + F (Eq. 57 with u = (j + F/2)/rho), formed from j directly.  Each edge pair gets
+    // H_a +- H_b with H = G/12, and each face pair the remainder G_a/2 - 4 H_a, so that the
+    // population momenta sum to G up to the rounding of single operations.  (Splitting G as
+    // G/6 per face and G/12 per edge with rounded constants would hand out (1 + 3e-8) G in
+    // single precision, a bias that compounds over many steps.)
+    const C Gx = fma(om, m.jx, F[0]), Gy = fma(om, m.jy, F[1]), Gz = fma(om, m.jz, F[2]);
+    const C Hx = Gx * C(1.0 / 12.0), Hy = Gy * C(1.0 / 12.0), Hz = Gz * C(1.0 / 12.0);
     const C xy = x2 * y2, xz = x2 * z2, yz = y2 * z2;
     const C ox = y2 + z2, oy = x2 + z2, oz = x2 + y2;
 
@@ -438,35 +447,35 @@ __device__ __forceinline__ void collide(C d[Q], C beta[NB], const PopMoments<C> 
     d[0] = fma(om1, d[0], fma(wd, third, -wr9 * fma(C(2), x2 + ox, C(6) * (xy + xz + yz))) - fc * C(0.5) * trS);
 
     // faces: pairs (1,3) x, (2,4) y, (5,6) z
-    auto face = [&](int ip, int im, C a2, C oa, C ua, C Saa, C Fa) {
+    auto face = [&](int ip, int im, C a2, C oa, C Ga, C Ha, C Saa) {
         const C P = fma(wr18, fma(C(2), a2 - oa, C(6) * a2 * oa), wd18) + fc4 * (Saa - t3);
-        const C M = fma(wr6, ua, fc6 * Fa);
+        const C M = fma(C(-4), Ha, C(0.5) * Ga);
         d[ip] = fma(om1, d[ip], P + M);
         d[im] = fma(om1, d[im], P - M);
     };
-    face(1, 3, x2, ox, ux, S[0], F[0]);
-    face(2, 4, y2, oy, uy, S[1], F[1]);
-    face(5, 6, z2, oz, uz, S[2], F[2]);
+    face(1, 3, x2, ox, Gx, Hx, S[0]);
+    face(2, 4, y2, oy, Gy, Hy, S[1]);
+    face(5, 6, z2, oz, Gz, Hz, S[2]);
 
     // edges: in the (a,b) plane, pairs (+a+b, -a-b) and (+a-b, -a+b)
-    auto edges = [&](int ipp, int imm, int ipm, int imp, C a2b2, C a2b2x, C ua, C ub, C Saa, C Sbb, C Sab, C Fa,
-                     C Fb) {
+    auto edges = [&](int ipp, int imm, int ipm, int imp, C a2b2, C a2b2x, C ua, C ub, C Ha, C Hb, C Saa, C Sbb,
+                     C Sab) {
         const C base = fma(-wr36, fma(C(6), a2b2x, a2b2), wd36) + fc8 * (Saa + Sbb - t3);
         const C sab = fc4 * Sab;
         C q = ua + ub;
         C P = fma(wr12, q * q, base) + sab;
-        C M = fma(wr12, q, fc12 * (Fa + Fb));
+        C M = Ha + Hb;
         d[ipp] = fma(om1, d[ipp], P + M);
         d[imm] = fma(om1, d[imm], P - M);
         q = ua - ub;
         P = fma(wr12, q * q, base) - sab;
-        M = fma(wr12, q, fc12 * (Fa - Fb));
+        M = Ha - Hb;
         d[ipm] = fma(om1, d[ipm], P + M);
         d[imp] = fma(om1, d[imp], P - M);
     };
-    edges(7, 10, 8, 9, oz, xy, ux, uy, S[0], S[1], S[3], F[0], F[1]);
-    edges(11, 14, 12, 13, oy, xz, ux, uz, S[0], S[2], S[4], F[0], F[2]);
-    edges(15, 18, 16, 17, ox, yz, uy, uz, S[1], S[2], S[5], F[1], F[2]);
+    edges(7, 10, 8, 9, oz, xy, ux, uy, Hx, Hy, S[0], S[1], S[3]);
+    edges(11, 14, 12, 13, oy, xz, ux, uz, Hx, Hz, S[0], S[2], S[4]);
+    edges(15, 18, 16, 17, ox, yz, uy, uz, Hy, Hz, S[1], S[2], S[5]);
 }
 
 // Periodic neighbour offsets of a site: X/Y/Z[d+1] hold the x index, the row offset and the

@@ -128,6 +128,13 @@ template <int S> struct Buf {
                                                      0x00020000);
         }
     }
+    // Byte offset of plane j (< PPG) inside its group.  It can reach 2^31 and beyond (a 512^3
+    // lattice puts plane 4 of a float group at 2^31 bytes), so it is formed in unsigned 32-bit
+    // arithmetic, exact below the group's 4 GiB (fused_supported_s), and handed to the buffer
+    // instruction's unsigned offset operand as the same 32 bits.
+    __device__ __forceinline__ int plane_offset(int j) const {
+        return (int)((unsigned)j * (unsigned)pb);
+    }
     // A value as loaded (the storage type), decoded only where it is used: a load whose result
     // is kept raw can be issued one plane ahead without the wait for it coming at the load.
     using R = T;
@@ -136,7 +143,7 @@ template <int S> struct Buf {
     template <int K, int POL = 0> __device__ __forceinline__ R loadraw(int off) const {
         constexpr int g = K / PPG, j = K % PPG;
         const __amdgpu_buffer_rsrc_t rs = r[g];
-        const int so = __builtin_amdgcn_readfirstlane(j * pb);
+        const int so = __builtin_amdgcn_readfirstlane(plane_offset(j));
         if constexpr (S == 0) {
             return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, so, POL));
         } else if constexpr (S == 1) {
@@ -161,11 +168,12 @@ template <int S> struct Buf {
         return decode<K, F0>(loadraw<K>(off), cd);
     }
     // Stores a value; for 16-bit codes, amax collects |code| so that one comparison after the
-    // sweep detects overflow (an overflowing code is stored as +-inf and reported as RANGE).
+    // sweep detects overflow (an overflowing code is stored as +-inf and reported as RANGE, the
+    // same rule as the other kernels' encoders).
     template <int K, int F0> __device__ __forceinline__ void storef(int off, C v, const Codec &cd, float &amax) const {
         constexpr int g = K / PPG, j = K % PPG;
         const __amdgpu_buffer_rsrc_t rs = r[g];
-        const int so = __builtin_amdgcn_readfirstlane(j * pb);
+        const int so = __builtin_amdgcn_readfirstlane(plane_offset(j));
         if constexpr (S == 0) {
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0)), v),
                                                   rs, off, so, 0);
@@ -647,12 +655,14 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
     __syncthreads();
 }
 
-// Overflow check of the 16-bit codes a thread stored.
+// Overflow check of the 16-bit codes a thread stored: amax is the largest |code value| before
+// rounding, and a code overflowed (was stored as +-inf) exactly when it reached the rounding
+// midpoint above the largest finite code (a NaN does not enter the maximum).
 template <int S> __device__ __forceinline__ void report_range(float amax, unsigned *flag) {
     if constexpr (S == 2) {
-        if (!(amax <= 65504.0f)) *flag = 1u;
+        if (amax >= HALF_OVERFLOW) *flag = 1u;
     } else if constexpr (S == 3) {
-        if (!(amax <= 3.3895e38f)) *flag = 1u;
+        if (amax >= bf16_overflow()) *flag = 1u;
     }
 }
 

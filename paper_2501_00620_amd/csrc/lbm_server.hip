@@ -296,15 +296,7 @@ int upload_tables(lbm_server *s) {
                 return 0;
             });
         }
-        const double omega = 1.0 / (h->p.tau + 0.5);
-        d.k.omega = (float)omega;
-        d.k.half_omega = (float)(0.5 * omega);
-        d.k.fcoef = (float)(1.0 - 0.5 * omega);
-        d.k.rho_ref = (float)h->p.rho_ref;
-        d.k.theta_ref = (float)(h->p.T_ref - 1.0 / 3.0);
-        d.k.K = (float)(h->p.rho_ref * (h->p.T_ref - 1.0 / 3.0));
-        d.k.om1 = (float)(1.0 - omega);
-        d.k.iso = h->p.mode == LBM_ISO;
+        d.k = step_const<float>(h);  // the constants lbm_step uses
         d.flag = h->flag;
         d.cd = h->codec;
         s->h_desc.push_back(d);

@@ -107,3 +107,19 @@ def riemann2d_request(rng, n=None, n_range=(64, 512), T0=T_REF):
     T = q_T[quad]
     u = np.stack([q_u[quad, 0], q_u[quad, 1], np.zeros_like(rho)])
     return rho, u, T
+
+
+def served_batch(n_requests=512, rate=50.0, seed=2024):
+    """The served batch: Poisson arrival times (rate per second), grid edges n ~ U{64..512} and
+    per-request field seeds, all drawn with numpy PCG64(seed).  Request k's fields are
+    served_request(sizes[k], field_seeds[k])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+    sizes = rng.integers(64, 513, size=n_requests)
+    field_seeds = rng.integers(0, 1 << 62, size=n_requests)
+    return arrivals, sizes, field_seeds
+
+
+def served_request(n, field_seed):
+    """Fields of one request of the served batch: an n x n x 1 four-quadrant Riemann problem."""
+    return riemann2d_request(np.random.Generator(np.random.PCG64(int(field_seed))), n=int(n))

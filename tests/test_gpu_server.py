@@ -142,3 +142,35 @@ def test_projected_and_d3q19_one_plane_requests_side_by_side():
                          (r3, alone((rho, u, T), 0.7, 33, "f32"))):
             for x, y in zip(srv.fetch(rid), ref):
                 np.testing.assert_array_equal(x, y)
+
+
+def test_smallest_served_requests_match_the_oracle():
+    # The three smallest requests of the served batch (512 four-quadrant Riemann problems,
+    # 2000 steps, tau = 0.8; FP32 storage), served as the batch serves them: projected D2Q9
+    # lattices with the codec centred on each request's mean density and temperature.  Each
+    # result is checked against the oracle's D3Q19 run of the same request: <= 1e-5 relative L2
+    # on rho, u and T; a request the GPU reports failed must diverge in the oracle as well.
+    import oracle
+    L = lbm()
+    steps, tau = 2000, 0.8
+    _, sizes, seeds = wl.served_batch()
+    order = np.argsort(sizes, kind="stable")[:3]
+    reqs = [wl.served_request(sizes[k], seeds[k]) for k in order]
+    with L.Server(budget_bytes=1 << 30, bundle_steps=50, storage="f32", health_every=10) as srv:
+        ids = [srv.submit(*f, tau=tau, steps=steps) for f in reqs]
+        status = [srv.wait(r, timeout=100) for r in ids]
+        got = [srv.fetch(r) if s == "done" else None for r, s in zip(ids, status)]
+    for k, f, st, res in zip(order, reqs, status, got):
+        n = f[0].shape[-1]
+        o = oracle.OracleLattice(n, n, 1, tau)
+        o.init(*f)
+        o.step(steps)
+        ro, uo, To = o.moments()
+        healthy = bool(np.all(np.isfinite(o.F)) and np.all(ro > 0))
+        print(f"request {k} n={n}: server {st}, oracle {'finite' if healthy else 'diverged'}", flush=True)
+        if st != "done":
+            assert not healthy, (k, n, st)
+            continue
+        errs = [np.linalg.norm(a - b) / np.linalg.norm(b) for a, b in zip(res, (ro, uo, To))]
+        print(f"  rel L2 rho {errs[0]:.2e} u {errs[1]:.2e} T {errs[2]:.2e}", flush=True)
+        assert max(errs) <= 1e-5, (k, n, errs)
