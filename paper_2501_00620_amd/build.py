@@ -1,7 +1,10 @@
 """Build liblbm.so in-tree for gfx950 with hipcc.
 
 Every HIP translation unit is compiled with packed FP32 instructions disabled
-(``-Xclang -target-feature -Xclang -packed-fp32-ops``).
+(``-Xclang -target-feature -Xclang -packed-fp32-ops``) and with ``-ffp-contract=on``: a multiply
+and an add are fused only where one source expression holds both, so each kernel that inlines
+the per-site arithmetic rounds it the same way (a served lattice steps bit for bit as it would
+alone, whatever the surrounding kernel).
 """
 import os
 import subprocess
@@ -18,7 +21,7 @@ ARCH = "gfx950"
 
 def flags():
     return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on",
             "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 
