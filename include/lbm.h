@@ -136,6 +136,18 @@ int lbm_get_stored(lbm_handle h, void *F, void *b, int *b_is_gathered, int on_de
  * 1/2 sum (sum_i fbar_i |e_i|^2 + rho tr bbar). */
 int lbm_invariants(lbm_handle h, double out[5]);
 
+/* For callers that cannot allocate device memory or wait (code under HIP graph capture, serving
+ * loops, hosts that forbid hipMalloc): the 5 values of lbm_invariants, bit for bit, computed
+ * without any device allocation.
+ *  - on_device = 1: out is a device pointer to 5 doubles on the lattice's GPU; the call only
+ *    enqueues the reduction on the lattice's stream and returns (no synchronisation).
+ *  - on_device = 0: out is host memory; the call waits for the result.
+ * The partial sums live in one static scratch array per GPU (256 KiB, held until the process
+ * ends) whose size does not depend on the lattice: at most 1024 work-groups stride over it.
+ * Every call on a GPU shares that array, so calls that overlap on one GPU (from other streams
+ * or threads) race.  Errors: ARG (null pointer, projected lattice), STATE, HIP. */
+int lbm_invariants_noalloc(lbm_handle h, double *out, int on_device);
+
 /* Health check: counts of sites with a non-finite stored value and with rho <= 0, and the
  * largest |u*| (uncorrected velocity).  counts and max_u are filled in whatever the result.
  * Returns LBM_ERR_RANGE if a 16-bit code overflowed since the state was set or last checked

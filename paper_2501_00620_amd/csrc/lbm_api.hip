@@ -369,6 +369,10 @@ int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out) {
     h->p = *p;
     h->n = (int)n;
     h->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(LBM_ERR_HIP, "hipGetDevice failed");
+    }
     const size_t sb = store_bytes(p->storage);
     hipError_t e = hipSuccess;
     for (int b = 0; b < 2 && e == hipSuccess; b++) {

@@ -13,6 +13,7 @@
 struct lbm_lattice {
     lbm_params p{};
     hipStream_t stream = nullptr;
+    int device = 0;           // the HIP device the lattice was created on
     int n = 0;
     void *F[2] = {nullptr, nullptr};
     void *B[2] = {nullptr, nullptr};

@@ -48,6 +48,7 @@ SIGNATURES = {
     "lbm_get_raw": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
     "lbm_get_stored": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.c_int], C.c_int),
     "lbm_invariants": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
+    "lbm_invariants_noalloc": ([C.c_void_p, C.c_void_p, C.c_int], C.c_int),
     "lbm_health": ([C.c_void_p, C.POINTER(C.c_long), C.POINTER(C.c_double)], C.c_int),
     "lbm_set_kernel": ([C.c_void_p, C.c_int], C.c_int),
     "lbm_set_ghost_relaxation": ([C.c_void_p, C.c_double], C.c_int),
@@ -285,6 +286,19 @@ class Lattice:
         out = (C.c_double * 5)()
         _check(_lib.lbm_invariants(self._h, out))
         return np.array(out[:])
+
+    def invariants_noalloc(self, out=None):
+        """lbm_invariants_noalloc: into `out`, a CUDA float64 tensor of 5 (enqueued on the
+        lattice's stream, returned without waiting), or, if out is None, as a numpy array."""
+        if out is None:
+            res = (C.c_double * 5)()
+            _check(_lib.lbm_invariants_noalloc(self._h, C.cast(res, C.c_void_p), 0))
+            return np.array(res[:])
+        torch = _torch()
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < 5 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous CUDA float64 tensor of at least 5 elements")
+        _check(_lib.lbm_invariants_noalloc(self._h, C.c_void_p(out.data_ptr()), 1))
+        return out
 
     def health(self):
         """(n_nonfinite, n_rho_nonpositive, max|u*|); raises LBMError DIVERGED if unhealthy."""
