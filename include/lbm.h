@@ -155,11 +155,16 @@ int lbm_invariants_noalloc(lbm_handle h, double *out, int on_device);
 int lbm_health(lbm_handle h, long counts[2], double *max_u);
 
 /* Per-step launch configuration. kernel: 0 = auto, 1 = two-pass (predictor sources to a
- * buffer, then gradient + collision), 2 = fused z-marching sweep with LDS planes of sources.
- * Auto takes the fused sweep for a periodic lattice (with or without a body force) whose buffers
- * fit its 32-bit offsets, and the two-pass step for walls or a ghost rate.  Errors: ARG (bad
- * choice; the fused sweep on a projected lattice, on walls, with a ghost rate, or beyond its
- * offsets). */
+ * buffer, then gradient + collision), 2 = fused z-marching sweep with LDS planes of sources
+ * (every wave does every part of the step), 3 = the same sweep split between producer waves
+ * (predictor sources) and consumer waves (gradient, collision, stream) of one work-group, for
+ * float and 16-bit storage on lattices with nz >= 3.  All give the same step up to the order of
+ * the gradient sums.  Auto takes the split sweep where it applies (from the second step after
+ * the state was set; the first gathers bbar in the single-role sweep), else the single-role
+ * fused sweep, for a periodic lattice (with or without a body force) whose buffers fit their
+ * 32-bit offsets, and the two-pass step for walls or a ghost rate.  Errors: ARG (bad choice; a
+ * fused sweep on a projected lattice, on walls, with a ghost rate, or beyond its offsets; the
+ * split sweep in double precision or below 3 planes). */
 int lbm_set_kernel(lbm_handle h, int kernel);
 
 /* Relaxation time of the nine non-hydrodynamic moments, rows 11-19 of Table I (Appendix B):

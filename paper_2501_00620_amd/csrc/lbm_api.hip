@@ -14,6 +14,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_fused.hpp"
+#include "lbm_fused_ws.hpp"
 #include "lbm_internal.hpp"
 #include "lbm_kernels.hpp"
 #include "lbm_proj.hpp"
@@ -253,14 +254,34 @@ template <int S> int step_two_pass(lbm_lattice *h) {
     return LBM_OK;
 }
 
+// The producer/consumer sweep steps float and 16-bit lattices that march in z, once bbar is held
+// scattered (the first step after the state was set gathers it from global memory in the
+// single-role sweep); lbm_set_kernel(2) keeps the single-role sweep throughout.
+bool use_fused_ws(const lbm_lattice *h) {
+    return (h->kernel == 0 || h->kernel == 3) && !h->gathered && fused_ws_supported(geo(h), h->p.storage);
+}
+
 template <int S> int step_fused(lbm_lattice *h) {
     using T = typename Storage<S>::T;
     using C = typename Storage<S>::C;
     const Geo g = geo(h);
     const StepConst<C> k = step_const<C>(h);
-    int rc = launch_fused<S>((const T *)h->F[h->cur], (const T *)h->B[h->cur], (T *)h->F[1 - h->cur],
-                             (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->flag,
-                             h->gathered, h->slots, h->stream, (const C *)h->accel);
+    int rc = 0;
+    if constexpr (S != 0) {
+        if (use_fused_ws(h)) {
+            rc = launch_fused_ws<S>((const T *)h->F[h->cur], (const T *)h->B[h->cur], (T *)h->F[1 - h->cur],
+                                    (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->flag,
+                                    h->slots_ws, h->stream, (const C *)h->accel);
+            if (rc) return fail(LBM_ERR_HIP, "fused launch failed");
+            rc = check_launch();
+            if (rc) return rc;
+            h->cur = 1 - h->cur;
+            return LBM_OK;
+        }
+    }
+    rc = launch_fused<S>((const T *)h->F[h->cur], (const T *)h->B[h->cur], (T *)h->F[1 - h->cur],
+                         (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->flag,
+                         h->gathered, h->slots, h->stream, (const C *)h->accel);
     if (rc) return fail(LBM_ERR_HIP, "fused launch failed");
     rc = check_launch();
     if (rc) return rc;
@@ -403,6 +424,14 @@ int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out) {
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<S, false, false, false, false>,
                                                              TileFor<S>::type::NT, 0) != hipSuccess)
                 per_cu = 1;
+            if constexpr (S != 0) {
+                int ws = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&ws, k_fused_ws<S, false, false>, WS_THREADS, 0) !=
+                        hipSuccess ||
+                    ws < 1)
+                    ws = 1;
+                h->slots_ws = cus * ws;
+            }
             return LBM_OK;
         });
         h->slots = cus * (per_cu > 0 ? per_cu : 1);
@@ -430,13 +459,16 @@ void lbm_destroy(lbm_handle h) {
 }
 
 int lbm_set_kernel(lbm_handle h, int kernel) {
-    if (!h || kernel < 0 || kernel > 2) return fail(LBM_ERR_ARG, "bad kernel choice");
-    if (kernel == 2 && h->proj < 3) return fail(LBM_ERR_ARG, "projected lattices step with their own kernels");
-    if (kernel == 2 && !fused_supported(geo(h), h->p.storage))
+    if (!h || kernel < 0 || kernel > 3) return fail(LBM_ERR_ARG, "bad kernel choice");
+    const bool fused = kernel == 2 || kernel == 3;
+    if (fused && h->proj < 3) return fail(LBM_ERR_ARG, "projected lattices step with their own kernels");
+    if (fused && !fused_supported(geo(h), h->p.storage))
         return fail(LBM_ERR_ARG, "fused sweep does not support this lattice shape");
-    if (kernel == 2 && h->tau_ghost > 0.0)
+    if (fused && h->tau_ghost > 0.0)
         return fail(LBM_ERR_ARG, "the fused sweep relaxes with a single rate (a ghost rate is set)");
-    if (kernel == 2 && h->walls) return fail(LBM_ERR_ARG, "the fused sweep is periodic (walls are set)");
+    if (fused && h->walls) return fail(LBM_ERR_ARG, "the fused sweep is periodic (walls are set)");
+    if (kernel == 3 && !fused_ws_supported(geo(h), h->p.storage))
+        return fail(LBM_ERR_ARG, "the producer/consumer sweep takes float or 16-bit storage and nz >= 3");
     h->kernel = kernel;
     return LBM_OK;
 }
@@ -450,7 +482,8 @@ int lbm_set_walls(lbm_handle h, int on, const double *u_bottom, const double *u_
     }
     if (h->p.nz < 3) return fail(LBM_ERR_ARG, "walls need nz >= 3 (got %d)", h->p.nz);
     if (h->proj < 3) return fail(LBM_ERR_ARG, "projected lattices have no walls");
-    if (h->kernel == 2) return fail(LBM_ERR_ARG, "the fused sweep is periodic (lbm_set_kernel chose it)");
+    if (h->kernel == 2 || h->kernel == 3)
+        return fail(LBM_ERR_ARG, "the fused sweep is periodic (lbm_set_kernel chose it)");
     double uw[6] = {0, 0, 0, 0, 0, 0};
     for (int c = 0; c < 3; c++) {
         if (u_bottom) uw[c] = u_bottom[c];
@@ -473,7 +506,8 @@ int lbm_set_projection(lbm_handle h, int dims) {
     if (dims == 1 && (h->p.ny != 1 || h->p.nz != 1)) return fail(LBM_ERR_ARG, "a D1Q3 projection needs ny = nz = 1");
     if (dims < 3) {
         if (h->p.mode == LBM_STANDARD) return fail(LBM_ERR_ARG, "the standard comparator is not projected");
-        if (h->kernel == 2) return fail(LBM_ERR_ARG, "projected lattices step with their own two-pass kernels");
+        if (h->kernel == 2 || h->kernel == 3)
+            return fail(LBM_ERR_ARG, "projected lattices step with their own two-pass kernels");
         if (h->walls || h->accel || h->tau_ghost > 0.0)
             return fail(LBM_ERR_ARG, "projected lattices have no walls, body force or ghost rate");
     }
@@ -573,7 +607,7 @@ int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost) {
     if (!(tau_ghost > 0.0) || !std::isfinite(tau_ghost)) return fail(LBM_ERR_ARG, "tau_ghost must be > 0");
     if (h->p.mode == LBM_STANDARD) return fail(LBM_ERR_ARG, "the standard comparator relaxes with a single rate");
     if (h->proj < 3 && tau_ghost != h->p.tau) return fail(LBM_ERR_ARG, "projected lattices relax with a single rate");
-    if (h->kernel == 2 && tau_ghost != h->p.tau)
+    if ((h->kernel == 2 || h->kernel == 3) && tau_ghost != h->p.tau)
         return fail(LBM_ERR_ARG, "the fused sweep relaxes with a single rate (lbm_set_kernel chose it)");
     h->tau_ghost = tau_ghost == h->p.tau ? -1.0 : tau_ghost;
     return LBM_OK;

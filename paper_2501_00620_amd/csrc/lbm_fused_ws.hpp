@@ -1,0 +1,438 @@
+// lbm_fused_ws.hpp -- the fused sweep with producer and consumer waves (one launch per step).
+//
+// The same step as k_fused (Sec. II C: predictor sources, isotropic gradients, collision and the
+// stream with the bbar gather of Eq. 66), organised for occupancy.  A work-group of 1024 threads
+// owns a 64 x 8 xy tile and marches through a chunk of z planes with two kinds of waves:
+//   producers (waves 0-7, one tile site per thread, ring sites on the first threads) stage the
+//     post-collision bbar* of plane p+2 in LDS and evaluate the predictor sources (rho b and u*,
+//     Eqs. 59-61 with Eq. 68) of plane p over the tile and its one-site ring, gathering bbar with
+//     the arriving populations (Eq. 66); they hand each tile site's gathered bbar on through LDS;
+//   consumers (waves 8-15, one tile site per thread) take the isotropic gradient of the sources
+//     plane by plane: each source plane q adds its 3 x 3 in-plane neighbourhood to the gradient
+//     sums of the sites in planes q-1, q and q+1, so only the newest source plane lives in LDS and
+//     the sums of plane q-1 are complete once plane q is in.  They then collide plane q-1 and push
+//     it out.
+// Both kinds run in the same iteration, separated by one barrier per plane: producers of plane p
+// next to consumers of plane p-2.  Each kind keeps about half of the single-role sweep's live
+// values (108-114 VGPRs per lane, no spills), so every SIMD holds four waves (two of each kind)
+// to cover each other's LDS and memory waits.
+//
+// LDS: four bbar* staging planes (tile plus two rings), two source planes (tile plus one ring),
+// and three hand-off planes of gathered bbar: 162,720 B of the 163,840 B a CU has.
+// The consumers read the populations of the plane they collide a second time from global memory
+// (the producers read them three iterations earlier, mostly an L2 hit).
+#pragma once
+
+#include "lbm_fused.hpp"
+
+namespace lbm {
+
+// Gradient sums with the face weight folded in: T = 2 (face terms) + (edge terms), so that
+// F = -T_F / 12, S_aa = -T_Saa / 6 (the diagonal collects v_a u_a once) and S_ab = -T_Sab / 12,
+// the same moments as grad_finish (weights 1/18 and 1/36 of the isotropic difference).
+template <typename C> struct GradT {
+    C F[3], S[6];
+};
+
+template <typename C> __device__ __forceinline__ void gradt_zero(GradT<C> &a) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) a.F[c] = C(0);
+#pragma unroll
+    for (int c = 0; c < 6; c++) a.S[c] = C(0);
+}
+
+// Direction I's term for a neighbour with sources s: v = sum_a e_Ia R'_a. and, for the
+// second-moment source, w = v + K e_I (the constant rho_ref b_ref when HASK), as grad_add.
+template <typename C, int I, bool HASK>
+__device__ __forceinline__ void gradt_add(GradT<C> &a, const C s[NSRC], C K) {
+    constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
+    constexpr bool face = (ex * ex + ey * ey + ez * ez) == 1;
+    const C vx = C(ex) * s[0] + C(ey) * s[3] + C(ez) * s[4];
+    const C vy = C(ex) * s[3] + C(ey) * s[1] + C(ez) * s[5];
+    const C vz = C(ex) * s[4] + C(ey) * s[5] + C(ez) * s[2];
+    C wx = vx, wy = vy, wz = vz;
+    if constexpr (HASK) {
+        wx = vx + C(ex) * K;
+        wy = vy + C(ey) * K;
+        wz = vz + C(ez) * K;
+    }
+    if constexpr (face) {  // weight 2 (exact scaling)
+        wx = C(2) * wx;
+        wy = C(2) * wy;
+        wz = C(2) * wz;
+        a.F[0] = fma(C(2), vx, a.F[0]);
+        a.F[1] = fma(C(2), vy, a.F[1]);
+        a.F[2] = fma(C(2), vz, a.F[2]);
+    } else {
+        a.F[0] += vx;
+        a.F[1] += vy;
+        a.F[2] += vz;
+    }
+    const C ux = s[6], uy = s[7], uz = s[8];
+    a.S[0] = fma(wx, ux, a.S[0]);
+    a.S[1] = fma(wy, uy, a.S[1]);
+    a.S[2] = fma(wz, uz, a.S[2]);
+    a.S[3] = fma(wx, uy, fma(wy, ux, a.S[3]));
+    a.S[4] = fma(wx, uz, fma(wz, ux, a.S[4]));
+    a.S[5] = fma(wy, uz, fma(wz, uy, a.S[5]));
+}
+
+template <typename C> __device__ __forceinline__ void gradt_finish(const GradT<C> &a, C F[3], C S[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) F[c] = -a.F[c] * C(1.0 / 12.0);
+#pragma unroll
+    for (int c = 0; c < 3; c++) S[c] = -a.S[c] * C(1.0 / 6.0);
+#pragma unroll
+    for (int c = 3; c < 6; c++) S[c] = -a.S[c] * C(1.0 / 12.0);
+}
+
+// Index of the D3Q19 velocity (ex, ey, ez), or -1.
+constexpr int dir_index(int ex, int ey, int ez) {
+    for (int i = 0; i < Q; i++)
+        if (EX[i] == ex && EY[i] == ey && EZ[i] == ez) return i;
+    return -1;
+}
+
+// Sources of one site whose bbar* neighbourhood is staged in LDS, as source_site_staged, with the
+// gather's partial sums pinned in registers after every PC_GATHER_GROUP directions.  Left free, the
+// compiler issues all 114 LDS reads of the gather first and sinks the multiply-adds below them
+// (they wait on the populations' loads), which needs far more than the 128 registers a lane has
+// at four waves per SIMD; the empty asm statements, which only claim to read and write the
+// partial sums, keep each group's reads next to their use.
+#ifndef PC_GATHER_GROUP
+#define PC_GATHER_GROUP 2
+#endif
+#ifndef PC_GRAD_GROUP
+#define PC_GRAD_GROUP 3
+#endif
+template <typename C> __device__ __forceinline__ void pin(C &v) { asm volatile("" : "+v"(v)); }
+
+template <int S, typename TL, bool KEEP>
+__device__ __forceinline__ void source_site_pc(const Buf<S> &bF, const typename Buf<S>::R raw[Q],
+                                               const typename Storage<S>::C *__restrict__ Tf,
+                                               typename Storage<S>::C Tconst,
+                                               const StepConst<typename Storage<S>::C> &k, const Codec &cd,
+                                               int s, int bidx, const typename Storage<S>::C *const bs[3],
+                                               typename Storage<S>::C *plane, int lidx,
+                                               SiteState<typename Storage<S>::C> &keep) {
+    using C = typename Storage<S>::C;
+    C d[Q], beta[NB];
+    Unroll<0, Q>::run([&](auto I) { d[I] = bF.template decode<I, 0>(raw[I], cd); });
+    const PopMoments<C> m = pop_moments(d, k.rho_ref);
+    C acc[NB];
+#pragma unroll
+    for (int c = 0; c < NB; c++) acc[c] = C(0);
+    Unroll<0, Q>::run([&](auto I) {
+        constexpr int ex = EX[I], ey = EY[I], ez = EZ[I];
+        const C *pl = bs[1 - ez] + bidx;  // upstream site y - e_i lies in plane z - e_iz
+        constexpr int off = -ey * TL::BX - ex;
+        const C wgt = fma(C(WQ[I]), k.rho_ref, d[I]);
+#pragma unroll
+        for (int c = 0; c < NB; c++) acc[c] = fma(wgt, pl[c * TL::NB2 + off], acc[c]);
+        if constexpr (I % PC_GATHER_GROUP == PC_GATHER_GROUP - 1) {
+#pragma unroll
+            for (int c = 0; c < NB; c++) pin(acc[c]);
+        }
+    });
+    const C inv = recip(m.rho);
+#pragma unroll
+    for (int c = 0; c < NB; c++) beta[c] = acc[c] * inv;
+    const C th = site_T(Tf, Tconst, s);
+    C o[NSRC];
+    predictor_sources(m, beta, th, k, o);
+#pragma unroll
+    for (int c = 0; c < NSRC; c++) plane[c * TL::NS + lidx] = o[c];
+    if constexpr (KEEP) {
+#pragma unroll
+        for (int c = 0; c < NB; c++) keep.beta[c] = beta[c];
+        keep.theta = th;
+    }
+}
+
+using WsTile = Tile<64, 8>;
+constexpr int WS_THREADS = 2 * WsTile::NT;
+
+// LDS of one work-group (bytes), checked against the 160 KiB of a CU.
+constexpr size_t ws_lds_bytes() {
+    return sizeof(float) * (4 * (size_t)NB * WsTile::NB2 + 2 * (size_t)NSRC * WsTile::NS + 3 * (size_t)NB * WsTile::NT);
+}
+static_assert(ws_lds_bytes() <= 163840, "producer/consumer sweep exceeds the LDS of a CU");
+
+template <int S, bool HASK, bool FORCE>
+__global__ void __launch_bounds__(WS_THREADS)
+k_fused_ws(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
+           typename Storage<S>::T *__restrict__ Fo, typename Storage<S>::T *__restrict__ Bo,
+           const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
+           StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag, FusedGeo fg,
+           const typename Storage<S>::C *__restrict__ accel) {
+    static_assert(S != 0, "double precision keeps the single-role sweep");
+    using C = typename Storage<S>::C;
+    using T = typename Storage<S>::T;
+    using R = typename Buf<S>::R;
+    using TL = WsTile;
+    constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT, NS = TL::NS, NB2 = TL::NB2;
+    constexpr int NSTAGE = (NB2 + NT - 1) / NT;
+    constexpr int NRING = (TL::NH + NT - 1) / NT;
+    constexpr int SB = (int)sizeof(T);
+    __shared__ C bst[4][NB * NB2];     // staged bbar*, by plane mod 4
+    __shared__ C lsrc[2][NSRC * NS];   // sources, by plane mod 2
+    __shared__ C hand[3][NB * NT];     // gathered bbar of the tile sites, by plane mod 3
+
+    // XCD-aware work-group numbering, as k_fused
+    const int nblk = gridDim.x;
+    int L = blockIdx.x;
+    if ((nblk & 7) == 0) L = (L & 7) * (nblk >> 3) + (L >> 3);
+    const int tx = L % fg.tiles_x;
+    L /= fg.tiles_x;
+    const int ty = L % fg.tiles_y;
+    const int chunk = L / fg.tiles_y;
+
+    Buf<S> bF, bB, bFo, bBo;
+    bF.init(F, Q, g.n);
+    bB.init(B, NB, g.n);
+    bFo.init(Fo, Q, g.n);
+    bBo.init(Bo, NB, g.n);
+
+    const int z0 = chunk * fg.zchunk;
+    const int z1 = min(z0 + fg.zchunk, g.nz);
+    const int nxy = g.nx * g.ny;
+    const bool producer = threadIdx.x < NT;
+    const int t = threadIdx.x & (NT - 1);
+
+    // the thread's tile site
+    const int lx = t % TX, ly = t / TX;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool inside = gx < g.nx && gy < g.ny;
+    const int wx = wrapc(gx, g.nx), wy = wrapc(gy, g.ny);
+    const int ixy = wy * g.nx + wx;
+    const int iidx = (ly + 1) * TL::HX + (lx + 1);
+    const int ibidx = (ly + 2) * TL::BX + (lx + 2);
+
+    // slots of plane q (q >= z0 - 2): staging q mod 4, sources q mod 2, hand-off q mod 3
+    auto sslot = [&](int q) { return (q - z0 + 8) & 3; };
+    auto cslot = [&](int q) { return (q - z0 + 8) & 1; };
+    auto hslot = [&](int q) { return (q - z0 + 9) % 3; };
+    auto zoff = [&](int q) { return wrapc(q, g.nz) * nxy; };
+
+    float amax = 0.0f;
+
+    if (producer) {
+        // ring sites and staging sites of this thread
+        int rxy[NRING], rlidx[NRING], rbidx[NRING];
+#pragma unroll
+        for (int j = 0; j < NRING; j++) {
+            const int h = t + j * NT;
+            int rlx = 0, rly = 0;
+            if (h < TL::HX) {
+                rly = -1;
+                rlx = h - 1;
+            } else if (h < 2 * TL::HX) {
+                rly = TY;
+                rlx = h - TL::HX - 1;
+            } else if (h < 2 * TL::HX + TY) {
+                rlx = -1;
+                rly = h - 2 * TL::HX;
+            } else {
+                rlx = TX;
+                rly = h - 2 * TL::HX - TY;
+            }
+            rxy[j] = wrapc(y0 + rly, g.ny) * g.nx + wrapc(x0 + rlx, g.nx);
+            rlidx[j] = (rly + 1) * TL::HX + (rlx + 1);
+            rbidx[j] = (rly + 2) * TL::BX + (rlx + 2);
+        }
+        int sxy[NSTAGE];
+#pragma unroll
+        for (int j = 0; j < NSTAGE; j++) {
+            const int r = t + j * NT;
+            const int bx = r % TL::BX - 2, by = r / TL::BX - 2;
+            sxy[j] = wrapc(y0 + by, g.ny) * g.nx + wrapc(x0 + bx, g.nx);
+        }
+        R sraw[NSTAGE][NB];
+        R praw[Q];
+        auto stage_issue = [&](int q) {
+            const int zo = zoff(q);
+#pragma unroll
+            for (int j = 0; j < NSTAGE; j++) {
+                if (t + j * NT < NB2) {
+                    const int off = (zo + sxy[j]) * SB;
+                    Unroll<0, NB>::run([&](auto c) { sraw[j][c] = bB.template loadraw<c>(off); });
+                }
+            }
+        };
+        auto stage_commit = [&](int q) {
+            C *dst = bst[sslot(q)];
+#pragma unroll
+            for (int j = 0; j < NSTAGE; j++) {
+                const int r = t + j * NT;
+                if (r < NB2) {
+                    Unroll<0, NB>::run([&](auto c) { dst[c * NB2 + r] = bB.template decode<c, Q>(sraw[j][c], cd); });
+                }
+            }
+        };
+        auto pops_issue = [&](int p) {
+            const int off = (zoff(p) + ixy) * SB;
+            Unroll<0, Q>::run([&](auto I) { praw[I] = bF.template loadraw<I>(off); });
+        };
+
+        // prologue: staged planes z0-2 .. z0 in LDS, z0+1 and the populations of z0-1 loading
+        for (int q = z0 - 2; q <= z0; q++) {
+            stage_issue(q);
+            stage_commit(q);
+        }
+        stage_issue(z0 + 1);
+        pops_issue(z0 - 1);
+        __syncthreads();
+        for (int p = z0 - 1; p <= z1 + 1; p++) {
+            if (p <= z1) {
+                // staged plane p+2 for the next iteration (its slot last served plane p-2)
+                if (p + 2 <= z1 + 1) {
+                    stage_commit(p + 2);
+                    if (p + 3 <= z1 + 1) stage_issue(p + 3);
+                }
+                const C *bs[3] = {bst[sslot(p - 1)], bst[sslot(p)], bst[sslot(p + 1)]};
+                C *plane = lsrc[cslot(p)];
+                const int zo = zoff(p);
+                SiteState<C> keep;
+                source_site_pc<S, TL, true>(bF, praw, Tf, Tconst, k, cd, zo + ixy, ibidx, bs, plane, iidx, keep);
+                C *hd = hand[hslot(p)];
+#pragma unroll
+                for (int c = 0; c < NB; c++) hd[c * NT + t] = keep.beta[c];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int j = 0; j < NRING; j++) {
+                    if (t + j * NT < TL::NH) {
+                        R rraw[Q];
+                        const int roff = (zo + rxy[j]) * SB;
+                        Unroll<0, Q>::run([&](auto I) { rraw[I] = bF.template loadraw<I>(roff); });
+                        SiteState<C> dummy;
+                        source_site_pc<S, TL, false>(bF, rraw, Tf, Tconst, k, cd, zo + rxy[j], rbidx[j], bs, plane,
+                                                         rlidx[j], dummy);
+                    }
+                }
+                if (p + 1 <= z1) pops_issue(p + 1);
+            }
+            __syncthreads();
+        }
+    } else {
+        // push targets of the tile site: x and y offsets of its 3 x 3 neighbourhood (periodic)
+        int Xo[3], Yo[3];
+        Xo[0] = wx == 0 ? g.nx - 1 : wx - 1;
+        Xo[1] = wx;
+        Xo[2] = wx == g.nx - 1 ? 0 : wx + 1;
+        Yo[0] = (wy == 0 ? g.ny - 1 : wy - 1) * g.nx;
+        Yo[1] = wy * g.nx;
+        Yo[2] = (wy == g.ny - 1 ? 0 : wy + 1) * g.nx;
+        GradT<C> A0, A1, A2;  // gradient sums of planes q-1, q, q+1
+        gradt_zero(A0);
+        gradt_zero(A1);
+        gradt_zero(A2);
+        __syncthreads();  // the producers' prologue
+        for (int p = z0 - 1; p <= z1 + 1; p++) {
+            const int q = p - 1;  // the source plane the producers finished last iteration
+            if (q >= z0 - 1) {
+                const int zc = zoff(q - 1);
+                const bool out = inside && q - 1 >= z0;
+                // the populations of plane q-1, read again for its collision (their last use:
+                // non-temporal in single precision)
+                constexpr int POL = S == 1 ? 2 : 0;
+                R craw[Q];
+                if (out) {
+                    const int off = (zc + ixy) * SB;
+                    Unroll<0, Q>::run([&](auto I) { craw[I] = bF.template loadraw<I, POL>(off); });
+                }
+                // source plane q: its 3 x 3 neighbourhood adds to the sums of planes q-1, q, q+1
+                const C *pl = lsrc[cslot(q)] + iidx;
+                Unroll<0, 9>::run([&](auto O) {
+                    constexpr int dx = (int)O % 3 - 1, dy = (int)O / 3 - 1;
+                    C sv[NSRC];
+#pragma unroll
+                    for (int c = 0; c < NSRC; c++) sv[c] = pl[c * NS + dy * TL::HX + dx];
+                    constexpr int dn = dir_index(dx, dy, 1);   // from a site of plane q-1
+                    constexpr int d0 = dir_index(dx, dy, 0);   // from a site of plane q
+                    constexpr int up = dir_index(dx, dy, -1);  // from a site of plane q+1
+                    if constexpr (dn > 0) gradt_add<C, dn, HASK>(A0, sv, k.K);
+                    if constexpr (d0 > 0) gradt_add<C, d0, HASK>(A1, sv, k.K);
+                    if constexpr (up > 0) gradt_add<C, up, HASK>(A2, sv, k.K);
+                    if constexpr (O % PC_GRAD_GROUP == PC_GRAD_GROUP - 1) {  // as in the gather
+#pragma unroll
+                        for (int c = 0; c < 3; c++) {
+                            pin(A0.F[c]);
+                            pin(A1.F[c]);
+                            pin(A2.F[c]);
+                        }
+#pragma unroll
+                        for (int c = 0; c < 6; c++) {
+                            pin(A0.S[c]);
+                            pin(A1.S[c]);
+                            pin(A2.S[c]);
+                        }
+                    }
+                });
+                if (out) {
+                    C Fv[3], Sv[6];
+                    gradt_finish(A0, Fv, Sv);
+                    C d[Q];
+                    Unroll<0, Q>::run([&](auto I) { d[I] = bF.template decode<I, 0>(craw[I], cd); });
+                    SiteState<C> cur;
+                    const C *hd = hand[hslot(q - 1)];
+#pragma unroll
+                    for (int c = 0; c < NB; c++) cur.beta[c] = hd[c * NT + t];
+                    const int s = zc + ixy;
+                    cur.theta = site_T(Tf, Tconst, s);
+                    const PopMoments<C> m = pop_moments(d, k.rho_ref);
+                    if constexpr (FORCE) {
+                        const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
+                        add_body_force(m, a, Fv, Sv);
+                    }
+                    collide(d, cur.beta, m, Fv, Sv, cur.theta, k);
+                    const int wz = wrapc(q - 1, g.nz);
+                    int Zo[3];
+                    Zo[0] = (wz == 0 ? g.nz - 1 : wz - 1) * nxy;
+                    Zo[1] = zc;
+                    Zo[2] = (wz == g.nz - 1 ? 0 : wz + 1) * nxy;
+                    Unroll<0, Q>::run([&](auto I) {
+                        const int tt = Zo[EZ[I] + 1] + Yo[EY[I] + 1] + Xo[EX[I] + 1];
+                        bFo.template storef<I, 0>(tt * SB, d[I], cd, amax);
+                    });
+                    Unroll<0, NB>::run([&](auto c) { bBo.template storef<c, Q>(s * SB, cur.beta[c], cd, amax); });
+                }
+                A0 = A1;
+                A1 = A2;
+                gradt_zero(A2);
+            }
+            __syncthreads();
+        }
+    }
+    report_range<S>(amax, flag);
+}
+
+// Resident work-groups per CU of the producer/consumer sweep: one (its LDS).
+template <int S>
+int launch_fused_ws(const typename Storage<S>::T *F, const typename Storage<S>::T *B, typename Storage<S>::T *Fo,
+                    typename Storage<S>::T *Bo, const typename Storage<S>::C *Tf, typename Storage<S>::C Tconst,
+                    const Geo &g, const StepConst<typename Storage<S>::C> &k, const Codec &cd, unsigned *flag, int slots,
+                    hipStream_t stream, const typename Storage<S>::C *accel = nullptr) {
+    const FusedGeo fg = fused_geometry_t<WsTile>(g, slots);
+    const long long blocks = (long long)fg.tiles_x * fg.tiles_y * fg.nchunks;
+    if (blocks > 2147483647LL) return -1;
+    const dim3 grid((unsigned)blocks), block(WS_THREADS);
+    const bool hask = k.K != 0;
+    auto go = [&](auto H, auto FO) {
+        hipLaunchKernelGGL((k_fused_ws<S, decltype(H)::value, decltype(FO)::value>), grid, block, 0, stream, F, B, Fo,
+                           Bo, Tf, Tconst, g, k, cd, flag, fg, accel);
+    };
+    using tt = std::true_type;
+    using ff = std::false_type;
+    if (accel) hask ? go(tt{}, tt{}) : go(ff{}, tt{});
+    else hask ? go(tt{}, ff{}) : go(ff{}, ff{});
+    return 0;
+}
+
+// Shapes the producer/consumer sweep takes: float and 16-bit storage, more than two z planes
+// (it marches), buffers within the fused sweep's 32-bit offsets.
+inline bool fused_ws_supported(const Geo &g, int storage) {
+    return storage != 0 && g.nz >= 3 && !g.walls && fused_supported(g, storage);
+}
+
+}  // namespace lbm

@@ -19,7 +19,7 @@ LBM_OK = 0
 ERRORS = {-1: "ARG", -2: "OOM", -3: "HIP", -4: "DIVERGED", -5: "RANGE", -6: "BUSY", -7: "STATE"}
 STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3}
 MODE = {"thermal": 0, "iso": 1, "standard": 2}
-KERNEL = {"auto": 0, "two_pass": 1, "fused": 2}
+KERNEL = {"auto": 0, "two_pass": 1, "fused": 2, "fused_pc": 3}
 
 
 class LBMError(RuntimeError):

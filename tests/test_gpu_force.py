@@ -106,7 +106,8 @@ def test_fused_equals_two_pass_with_force(storage, dims):
     fields = wl.fourier_fields(*dims, seed=12, u_max=0.25)
     accel = force_field(dims, 13)
     out = []
-    for kernel in ("fused", "two_pass"):
+    kernels = ("fused", "two_pass") + (("fused_pc",) if storage != "f64" and dims[2] >= 3 else ())
+    for kernel in kernels:
         g = lbm().Lattice(*dims, 0.65, storage=storage, kernel=kernel)
         g.set_fields(*fields)
         g.set_body_force(accel)
@@ -114,8 +115,9 @@ def test_fused_equals_two_pass_with_force(storage, dims):
         F, b = g.get_state()
         out.append((F.cpu().numpy(), b.cpu().numpy()))
     tol = {"f64": 1e-14, "f32": 1e-6, "f16dev": 1e-3, "bf16dev": 1e-2}[storage]
-    assert rel_l2(out[0][0], out[1][0]) <= tol
-    assert rel_l2(out[0][1], out[1][1]) <= tol
+    for k in (0, 2)[:len(out) - 1]:
+        assert rel_l2(out[k][0], out[1][0]) <= tol, kernels[k]
+        assert rel_l2(out[k][1], out[1][1]) <= tol, kernels[k]
     # and the force changes the result by far more than the bar (the comparison is not vacuous;
     # over 7 steps the force moves the state by ~1e-4, under the 16-bit bars, so checked where
     # the bar is tight)
