@@ -14,7 +14,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_fused.hpp"
-#include "lbm_fused_ws.hpp"
+#include "lbm_fused_pc.hpp"
 #include "lbm_internal.hpp"
 #include "lbm_kernels.hpp"
 #include "lbm_proj.hpp"
@@ -257,8 +257,8 @@ template <int S> int step_two_pass(lbm_lattice *h) {
 // The producer/consumer sweep steps float and 16-bit lattices that march in z, once bbar is held
 // scattered (the first step after the state was set gathers it from global memory in the
 // single-role sweep); lbm_set_kernel(2) keeps the single-role sweep throughout.
-bool use_fused_ws(const lbm_lattice *h) {
-    return (h->kernel == 0 || h->kernel == 3) && !h->gathered && fused_ws_supported(geo(h), h->p.storage);
+bool use_fused_pc(const lbm_lattice *h) {
+    return (h->kernel == 0 || h->kernel == 3) && !h->gathered && fused_pc_supported(geo(h), h->p.storage);
 }
 
 template <int S> int step_fused(lbm_lattice *h) {
@@ -268,10 +268,10 @@ template <int S> int step_fused(lbm_lattice *h) {
     const StepConst<C> k = step_const<C>(h);
     int rc = 0;
     if constexpr (S != 0) {
-        if (use_fused_ws(h)) {
-            rc = launch_fused_ws<S>((const T *)h->F[h->cur], (const T *)h->B[h->cur], (T *)h->F[1 - h->cur],
+        if (use_fused_pc(h)) {
+            rc = launch_fused_pc<S>((const T *)h->F[h->cur], (const T *)h->B[h->cur], (T *)h->F[1 - h->cur],
                                     (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->flag,
-                                    h->slots_ws, h->stream, (const C *)h->accel);
+                                    h->slots_pc, h->stream, (const C *)h->accel);
             if (rc) return fail(LBM_ERR_HIP, "fused launch failed");
             rc = check_launch();
             if (rc) return rc;
@@ -425,12 +425,12 @@ int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out) {
                                                              TileFor<S>::type::NT, 0) != hipSuccess)
                 per_cu = 1;
             if constexpr (S != 0) {
-                int ws = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&ws, k_fused_ws<S, false, false>, WS_THREADS, 0) !=
+                int per_cu_pc = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_pc, k_fused_pc<S, false, false>, PC_THREADS, 0) !=
                         hipSuccess ||
-                    ws < 1)
-                    ws = 1;
-                h->slots_ws = cus * ws;
+                    per_cu_pc < 1)
+                    per_cu_pc = 1;
+                h->slots_pc = cus * per_cu_pc;
             }
             return LBM_OK;
         });
@@ -467,7 +467,7 @@ int lbm_set_kernel(lbm_handle h, int kernel) {
     if (fused && h->tau_ghost > 0.0)
         return fail(LBM_ERR_ARG, "the fused sweep relaxes with a single rate (a ghost rate is set)");
     if (fused && h->walls) return fail(LBM_ERR_ARG, "the fused sweep is periodic (walls are set)");
-    if (kernel == 3 && !fused_ws_supported(geo(h), h->p.storage))
+    if (kernel == 3 && !fused_pc_supported(geo(h), h->p.storage))
         return fail(LBM_ERR_ARG, "the producer/consumer sweep takes float or 16-bit storage and nz >= 3");
     h->kernel = kernel;
     return LBM_OK;

@@ -140,10 +140,12 @@ template <int S> struct Buf {
     using R = T;
     // plane K of this array: its byte offset in its group goes to the scalar-offset operand
     // through readfirstlane, so it is known to be wave-uniform.  POL: cache-policy bits.
-    template <int K, int POL = 0> __device__ __forceinline__ R loadraw(int off) const {
+    // zoff: a further byte offset the whole wavefront shares (a plane of the lattice), added to
+    // the scalar operand so that the per-lane offset can stay fixed from plane to plane.
+    template <int K, int POL = 0> __device__ __forceinline__ R loadraw(int off, int zoff = 0) const {
         constexpr int g = K / PPG, j = K % PPG;
         const __amdgpu_buffer_rsrc_t rs = r[g];
-        const int so = __builtin_amdgcn_readfirstlane(plane_offset(j));
+        const int so = __builtin_amdgcn_readfirstlane((int)((unsigned)plane_offset(j) + (unsigned)zoff));
         if constexpr (S == 0) {
             return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, so, POL));
         } else if constexpr (S == 1) {
@@ -159,7 +161,10 @@ template <int S> struct Buf {
         if constexpr (S == 0 || S == 1) {
             return v;
         } else if constexpr (S == 2) {
-            return cd.scale[F0] * half_bits_to_float(v);
+            // scale x code as a multiply-add with a zero addend: one mixed-precision FMA that
+            // reads the fp16 code directly, instead of a conversion and a multiply (the product
+            // is exact in float; only a zero's sign can differ)
+            return fmaf(cd.scale[F0], half_bits_to_float(v), 0.0f);
         } else {  // bf16 codes hold the deviation itself (unit scale)
             return bf16_bits_to_float(v);
         }
@@ -170,10 +175,11 @@ template <int S> struct Buf {
     // Stores a value; for 16-bit codes, amax collects |code| so that one comparison after the
     // sweep detects overflow (an overflowing code is stored as +-inf and reported as RANGE, the
     // same rule as the other kernels' encoders).
-    template <int K, int F0> __device__ __forceinline__ void storef(int off, C v, const Codec &cd, float &amax) const {
+    template <int K, int F0>
+    __device__ __forceinline__ void storef(int off, C v, const Codec &cd, float &amax, int zoff = 0) const {
         constexpr int g = K / PPG, j = K % PPG;
         const __amdgpu_buffer_rsrc_t rs = r[g];
-        const int so = __builtin_amdgcn_readfirstlane(plane_offset(j));
+        const int so = __builtin_amdgcn_readfirstlane((int)((unsigned)plane_offset(j) + (unsigned)zoff));
         if constexpr (S == 0) {
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0)), v),
                                                   rs, off, so, 0);

@@ -1,4 +1,4 @@
-// lbm_fused_ws.hpp -- the fused sweep with producer and consumer waves (one launch per step).
+// lbm_fused_pc.hpp -- the fused sweep with producer and consumer waves (one launch per step).
 //
 // The same step as k_fused (Sec. II C: predictor sources, isotropic gradients, collision and the
 // stream with the bbar gather of Eq. 66), organised for occupancy.  A work-group of 1024 threads
@@ -105,6 +105,10 @@ constexpr int dir_index(int ex, int ey, int ez) {
 #ifndef PC_GRAD_GROUP
 #define PC_GRAD_GROUP 3
 #endif
+// Producers load the populations of the next plane one iteration ahead of their sources.
+#ifndef PC_PREFETCH_POPS
+#define PC_PREFETCH_POPS 1
+#endif
 template <typename C> __device__ __forceinline__ void pin(C &v) { asm volatile("" : "+v"(v)); }
 
 template <int S, typename TL, bool KEEP>
@@ -149,18 +153,18 @@ __device__ __forceinline__ void source_site_pc(const Buf<S> &bF, const typename 
     }
 }
 
-using WsTile = Tile<64, 8>;
-constexpr int WS_THREADS = 2 * WsTile::NT;
+using PcTile = Tile<64, 8>;
+constexpr int PC_THREADS = 2 * PcTile::NT;
 
 // LDS of one work-group (bytes), checked against the 160 KiB of a CU.
-constexpr size_t ws_lds_bytes() {
-    return sizeof(float) * (4 * (size_t)NB * WsTile::NB2 + 2 * (size_t)NSRC * WsTile::NS + 3 * (size_t)NB * WsTile::NT);
+constexpr size_t pc_lds_bytes() {
+    return sizeof(float) * (4 * (size_t)NB * PcTile::NB2 + 2 * (size_t)NSRC * PcTile::NS + 3 * (size_t)NB * PcTile::NT);
 }
-static_assert(ws_lds_bytes() <= 163840, "producer/consumer sweep exceeds the LDS of a CU");
+static_assert(pc_lds_bytes() <= 163840, "producer/consumer sweep exceeds the LDS of a CU");
 
 template <int S, bool HASK, bool FORCE>
-__global__ void __launch_bounds__(WS_THREADS)
-k_fused_ws(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
+__global__ void __launch_bounds__(PC_THREADS)
+k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
            typename Storage<S>::T *__restrict__ Fo, typename Storage<S>::T *__restrict__ Bo,
            const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
            StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag, FusedGeo fg,
@@ -169,7 +173,7 @@ k_fused_ws(const typename Storage<S>::T *__restrict__ F, const typename Storage<
     using C = typename Storage<S>::C;
     using T = typename Storage<S>::T;
     using R = typename Buf<S>::R;
-    using TL = WsTile;
+    using TL = PcTile;
     constexpr int TX = TL::TX, TY = TL::TY, NT = TL::NT, NS = TL::NS, NB2 = TL::NB2;
     constexpr int NSTAGE = (NB2 + NT - 1) / NT;
     constexpr int NRING = (TL::NH + NT - 1) / NT;
@@ -241,22 +245,21 @@ k_fused_ws(const typename Storage<S>::T *__restrict__ F, const typename Storage<
             rlidx[j] = (rly + 1) * TL::HX + (rlx + 1);
             rbidx[j] = (rly + 2) * TL::BX + (rlx + 2);
         }
-        int sxy[NSTAGE];
+        int sxy[NSTAGE];  // byte offsets within a plane
 #pragma unroll
         for (int j = 0; j < NSTAGE; j++) {
             const int r = t + j * NT;
             const int bx = r % TL::BX - 2, by = r / TL::BX - 2;
-            sxy[j] = wrapc(y0 + by, g.ny) * g.nx + wrapc(x0 + bx, g.nx);
+            sxy[j] = (wrapc(y0 + by, g.ny) * g.nx + wrapc(x0 + bx, g.nx)) * SB;
         }
         R sraw[NSTAGE][NB];
         R praw[Q];
         auto stage_issue = [&](int q) {
-            const int zo = zoff(q);
+            const int zb = zoff(q) * SB;
 #pragma unroll
             for (int j = 0; j < NSTAGE; j++) {
                 if (t + j * NT < NB2) {
-                    const int off = (zo + sxy[j]) * SB;
-                    Unroll<0, NB>::run([&](auto c) { sraw[j][c] = bB.template loadraw<c>(off); });
+                    Unroll<0, NB>::run([&](auto c) { sraw[j][c] = bB.template loadraw<c>(sxy[j], zb); });
                 }
             }
         };
@@ -271,8 +274,8 @@ k_fused_ws(const typename Storage<S>::T *__restrict__ F, const typename Storage<
             }
         };
         auto pops_issue = [&](int p) {
-            const int off = (zoff(p) + ixy) * SB;
-            Unroll<0, Q>::run([&](auto I) { praw[I] = bF.template loadraw<I>(off); });
+            const int zb = zoff(p) * SB;
+            Unroll<0, Q>::run([&](auto I) { praw[I] = bF.template loadraw<I>(ixy * SB, zb); });
         };
 
         // prologue: staged planes z0-2 .. z0 in LDS, z0+1 and the populations of z0-1 loading
@@ -281,7 +284,9 @@ k_fused_ws(const typename Storage<S>::T *__restrict__ F, const typename Storage<
             stage_commit(q);
         }
         stage_issue(z0 + 1);
+#if PC_PREFETCH_POPS
         pops_issue(z0 - 1);
+#endif
         __syncthreads();
         for (int p = z0 - 1; p <= z1 + 1; p++) {
             if (p <= z1) {
@@ -290,6 +295,9 @@ k_fused_ws(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                     stage_commit(p + 2);
                     if (p + 3 <= z1 + 1) stage_issue(p + 3);
                 }
+#if !PC_PREFETCH_POPS
+                pops_issue(p);
+#endif
                 const C *bs[3] = {bst[sslot(p - 1)], bst[sslot(p)], bst[sslot(p + 1)]};
                 C *plane = lsrc[cslot(p)];
                 const int zo = zoff(p);
@@ -303,32 +311,40 @@ k_fused_ws(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                 for (int j = 0; j < NRING; j++) {
                     if (t + j * NT < TL::NH) {
                         R rraw[Q];
-                        const int roff = (zo + rxy[j]) * SB;
-                        Unroll<0, Q>::run([&](auto I) { rraw[I] = bF.template loadraw<I>(roff); });
+                        const int zb = zo * SB;
+                        Unroll<0, Q>::run([&](auto I) { rraw[I] = bF.template loadraw<I>(rxy[j] * SB, zb); });
                         SiteState<C> dummy;
                         source_site_pc<S, TL, false>(bF, rraw, Tf, Tconst, k, cd, zo + rxy[j], rbidx[j], bs, plane,
                                                          rlidx[j], dummy);
                     }
                 }
+#if PC_PREFETCH_POPS
                 if (p + 1 <= z1) pops_issue(p + 1);
+#endif
             }
             __syncthreads();
         }
     } else {
-        // push targets of the tile site: x and y offsets of its 3 x 3 neighbourhood (periodic)
-        int Xo[3], Yo[3];
-        Xo[0] = wx == 0 ? g.nx - 1 : wx - 1;
-        Xo[1] = wx;
-        Xo[2] = wx == g.nx - 1 ? 0 : wx + 1;
-        Yo[0] = (wy == 0 ? g.ny - 1 : wy - 1) * g.nx;
-        Yo[1] = wy * g.nx;
-        Yo[2] = (wy == g.ny - 1 ? 0 : wy + 1) * g.nx;
-        GradT<C> A0, A1, A2;  // gradient sums of planes q-1, q, q+1
-        gradt_zero(A0);
-        gradt_zero(A1);
-        gradt_zero(A2);
+        // push targets of the tile site: byte offsets of its 3 x 3 in-plane neighbourhood
+        // (periodic), fixed for the whole chunk; the target plane's offset is wave-uniform
+        int yx[9];
+        {
+            const int Xo[3] = {wx == 0 ? g.nx - 1 : wx - 1, wx, wx == g.nx - 1 ? 0 : wx + 1};
+            const int Yo[3] = {(wy == 0 ? g.ny - 1 : wy - 1) * g.nx, wy * g.nx, (wy == g.ny - 1 ? 0 : wy + 1) * g.nx};
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+#pragma unroll
+                for (int a = 0; a < 3; a++) yx[b * 3 + a] = (Yo[b] + Xo[a]) * SB;
+        }
+        GradT<C> X, Y, Z;  // gradient sums of three consecutive planes, roles rotating
+        gradt_zero(X);
+        gradt_zero(Y);
+        gradt_zero(Z);
         __syncthreads();  // the producers' prologue
-        for (int p = z0 - 1; p <= z1 + 1; p++) {
+        // One iteration with A0, A1, A2 the sums of planes q-1, q, q+1; A0 is then done and
+        // cleared, to serve as the next iteration's plane q+2.  Rotating the roles by argument
+        // order (the loop unrolled by three) moves no registers.
+        auto iter = [&](int p, GradT<C> &A0, GradT<C> &A1, GradT<C> &A2) {
             const int q = p - 1;  // the source plane the producers finished last iteration
             if (q >= z0 - 1) {
                 const int zc = zoff(q - 1);
@@ -338,8 +354,7 @@ k_fused_ws(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                 constexpr int POL = S == 1 ? 2 : 0;
                 R craw[Q];
                 if (out) {
-                    const int off = (zc + ixy) * SB;
-                    Unroll<0, Q>::run([&](auto I) { craw[I] = bF.template loadraw<I, POL>(off); });
+                    Unroll<0, Q>::run([&](auto I) { craw[I] = bF.template loadraw<I, POL>(ixy * SB, zc * SB); });
                 }
                 // source plane q: its 3 x 3 neighbourhood adds to the sums of planes q-1, q, q+1
                 const C *pl = lsrc[cslot(q)] + iidx;
@@ -392,34 +407,39 @@ k_fused_ws(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                     Zo[1] = zc;
                     Zo[2] = (wz == g.nz - 1 ? 0 : wz + 1) * nxy;
                     Unroll<0, Q>::run([&](auto I) {
-                        const int tt = Zo[EZ[I] + 1] + Yo[EY[I] + 1] + Xo[EX[I] + 1];
-                        bFo.template storef<I, 0>(tt * SB, d[I], cd, amax);
+                        bFo.template storef<I, 0>(yx[(EY[I] + 1) * 3 + EX[I] + 1], d[I], cd, amax, Zo[EZ[I] + 1] * SB);
                     });
-                    Unroll<0, NB>::run([&](auto c) { bBo.template storef<c, Q>(s * SB, cur.beta[c], cd, amax); });
+                    Unroll<0, NB>::run([&](auto c) { bBo.template storef<c, Q>(ixy * SB, cur.beta[c], cd, amax, zc * SB); });
                 }
-                A0 = A1;
-                A1 = A2;
-                gradt_zero(A2);
+                gradt_zero(A0);
             }
             __syncthreads();
+        };
+        int p = z0 - 1;
+        for (; p + 2 <= z1 + 1; p += 3) {
+            iter(p, X, Y, Z);
+            iter(p + 1, Y, Z, X);
+            iter(p + 2, Z, X, Y);
         }
+        if (p <= z1 + 1) iter(p++, X, Y, Z);
+        if (p <= z1 + 1) iter(p, Y, Z, X);
     }
     report_range<S>(amax, flag);
 }
 
 // Resident work-groups per CU of the producer/consumer sweep: one (its LDS).
 template <int S>
-int launch_fused_ws(const typename Storage<S>::T *F, const typename Storage<S>::T *B, typename Storage<S>::T *Fo,
+int launch_fused_pc(const typename Storage<S>::T *F, const typename Storage<S>::T *B, typename Storage<S>::T *Fo,
                     typename Storage<S>::T *Bo, const typename Storage<S>::C *Tf, typename Storage<S>::C Tconst,
                     const Geo &g, const StepConst<typename Storage<S>::C> &k, const Codec &cd, unsigned *flag, int slots,
                     hipStream_t stream, const typename Storage<S>::C *accel = nullptr) {
-    const FusedGeo fg = fused_geometry_t<WsTile>(g, slots);
+    const FusedGeo fg = fused_geometry_t<PcTile>(g, slots);
     const long long blocks = (long long)fg.tiles_x * fg.tiles_y * fg.nchunks;
     if (blocks > 2147483647LL) return -1;
-    const dim3 grid((unsigned)blocks), block(WS_THREADS);
+    const dim3 grid((unsigned)blocks), block(PC_THREADS);
     const bool hask = k.K != 0;
     auto go = [&](auto H, auto FO) {
-        hipLaunchKernelGGL((k_fused_ws<S, decltype(H)::value, decltype(FO)::value>), grid, block, 0, stream, F, B, Fo,
+        hipLaunchKernelGGL((k_fused_pc<S, decltype(H)::value, decltype(FO)::value>), grid, block, 0, stream, F, B, Fo,
                            Bo, Tf, Tconst, g, k, cd, flag, fg, accel);
     };
     using tt = std::true_type;
@@ -431,7 +451,7 @@ int launch_fused_ws(const typename Storage<S>::T *F, const typename Storage<S>::
 
 // Shapes the producer/consumer sweep takes: float and 16-bit storage, more than two z planes
 // (it marches), buffers within the fused sweep's 32-bit offsets.
-inline bool fused_ws_supported(const Geo &g, int storage) {
+inline bool fused_pc_supported(const Geo &g, int storage) {
     return storage != 0 && g.nz >= 3 && !g.walls && fused_supported(g, storage);
 }
 

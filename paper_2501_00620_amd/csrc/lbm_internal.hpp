@@ -30,7 +30,7 @@ struct lbm_lattice {
     unsigned *flag = nullptr;   // saturation flag
     int kernel = 0;
     int slots = 256;            // fused work-groups resident at once (one per CU)
-    int slots_ws = 256;         // the same for the producer/consumer sweep
+    int slots_pc = 256;         // the same for the producer/consumer sweep
     double tau_ghost = -1.0;    // relaxation time of Table I rows 11-19 (<= 0: the single rate)
     void *accel = nullptr;      // body-force acceleration, 3 planes of the compute type, or null
     int walls = 0;              // 1: walls normal to z bound the lattice (lbm_set_walls)
