@@ -57,6 +57,7 @@ VALUES_PER_LUP = 2 * (19 + 6)
 # The sources that define the fused sweep kernel and its compile flags: PMC counters taken on
 # other sources do not describe the kernel being timed.
 KERNEL_SOURCES = ("paper_2501_00620_amd/csrc/lbm_device.hpp", "paper_2501_00620_amd/csrc/lbm_fused.hpp",
+                  "paper_2501_00620_amd/csrc/lbm_fused_pc.hpp",
                   "paper_2501_00620_amd/build.py")
 
 
@@ -76,6 +77,15 @@ def traffic_from_profiles(kernel, workload, launch_sites):
     if rec.get("source_hash") != source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def step_kernel(kernel, storage, nz):
+    """The kernel that times the steady-state steps of an n^3 lattice (lbm_set_kernel's choice)."""
+    if kernel == "two_pass":
+        return "k_two_pass"
+    if kernel == "fused_pc" or (kernel == "auto" and storage != "f64" and nz >= 3):
+        return "k_fused_pc"
+    return "k_fused"
 
 
 def timed_windows(lat, steps, warmup, windows=5):
@@ -645,7 +655,7 @@ def main():
     mlups = sites / secs_step / 1e6
     bytes_per_step = sites * VALUES_PER_LUP * BYTES_PER_VALUE[args.storage]
     achieved = bytes_per_step / secs_step / 1e9
-    kname = "k_fused" if args.kernel in ("auto", "fused") else "k_two_pass"
+    kname = step_kernel(args.kernel, args.storage, n)
     workload = f"tgv{n}_{args.storage}"
     traffic = traffic_from_profiles(kname, workload, sites)
     del lat
