@@ -57,6 +57,7 @@ VALUES_PER_LUP = 2 * (19 + 6)
 # The sources that define the fused sweep kernel and its compile flags: PMC counters taken on
 # other sources do not describe the kernel being timed.
 KERNEL_SOURCES = ("paper_2501_00620_amd/csrc/lbm_device.hpp", "paper_2501_00620_amd/csrc/lbm_fused.hpp",
+                  "paper_2501_00620_amd/csrc/lbm_sweep.hip",
                   "paper_2501_00620_amd/csrc/lbm_fused_pc.hpp",
                   "paper_2501_00620_amd/build.py")
 

@@ -18,6 +18,7 @@
 #include "lbm_internal.hpp"
 #include "lbm_kernels.hpp"
 #include "lbm_proj.hpp"
+#include "lbm_sweeps.hpp"
 
 using namespace lbm;
 
@@ -420,18 +421,9 @@ int lbm_create(const lbm_params *p, void *hip_stream, lbm_handle *out) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
         int per_cu = 0;
         (void)dispatch_storage(p->storage, [&](auto SI) -> int {
-            constexpr int S = decltype(SI)::value;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<S, false, false, false, false>,
-                                                             TileFor<S>::type::NT, 0) != hipSuccess)
-                per_cu = 1;
-            if constexpr (S != 0) {
-                int per_cu_pc = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_pc, k_fused_pc<S, false, false>, PC_THREADS, 0) !=
-                        hipSuccess ||
-                    per_cu_pc < 1)
-                    per_cu_pc = 1;
-                h->slots_pc = cus * per_cu_pc;
-            }
+            int per_cu_pc = 0;
+            if (sweep_occupancy<decltype(SI)::value>(&per_cu, &per_cu_pc) != hipSuccess) per_cu = per_cu_pc = 1;
+            h->slots_pc = cus * (per_cu_pc > 0 ? per_cu_pc : 1);
             return LBM_OK;
         });
         h->slots = cus * (per_cu > 0 ? per_cu : 1);

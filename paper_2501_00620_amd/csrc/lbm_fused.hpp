@@ -751,38 +751,4 @@ inline bool fused_supported(const Geo &g, int storage) {
     }
 }
 
-template <int S>
-int launch_fused(const typename Storage<S>::T *F, const typename Storage<S>::T *B, typename Storage<S>::T *Fo,
-                 typename Storage<S>::T *Bo, const typename Storage<S>::C *Tf, typename Storage<S>::C Tconst,
-                 const Geo &g, const StepConst<typename Storage<S>::C> &k, const Codec &cd, unsigned *flag,
-                 bool gathered, int slots, hipStream_t stream, const typename Storage<S>::C *accel = nullptr) {
-    using TL = typename TileFor<S>::type;
-    const FusedGeo fg = fused_geometry<S>(g, slots);
-    const long long blocks = (long long)fg.tiles_x * fg.tiles_y * fg.nchunks;
-    if (blocks > 2147483647LL) return -1;
-    const dim3 grid((unsigned)blocks), block(TL::NT);
-    const bool hask = k.K != 0;
-    // one z plane: the instantiation with the in-plane gather and gradient (the serving kernel
-    // sweeps such lattices with the same arithmetic)
-    auto go = [&](auto G, auto H, auto T1) {
-        if (accel)
-            hipLaunchKernelGGL((k_fused<S, decltype(G)::value, decltype(H)::value, decltype(T1)::value, true>), grid,
-                               block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg, accel);
-        else
-            hipLaunchKernelGGL((k_fused<S, decltype(G)::value, decltype(H)::value, decltype(T1)::value, false>), grid,
-                               block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg, accel);
-    };
-    using tt = std::true_type;
-    using ff = std::false_type;
-    const bool thin1 = g.nz == 1;
-    if (gathered) {
-        if (hask) thin1 ? go(tt{}, tt{}, tt{}) : go(tt{}, tt{}, ff{});
-        else thin1 ? go(tt{}, ff{}, tt{}) : go(tt{}, ff{}, ff{});
-    } else {
-        if (hask) thin1 ? go(ff{}, tt{}, tt{}) : go(ff{}, tt{}, ff{});
-        else thin1 ? go(ff{}, ff{}, tt{}) : go(ff{}, ff{}, ff{});
-    }
-    return 0;
-}
-
 }  // namespace lbm

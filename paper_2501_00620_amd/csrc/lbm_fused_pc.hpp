@@ -427,28 +427,6 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
     report_range<S>(amax, flag);
 }
 
-// Resident work-groups per CU of the producer/consumer sweep: one (its LDS).
-template <int S>
-int launch_fused_pc(const typename Storage<S>::T *F, const typename Storage<S>::T *B, typename Storage<S>::T *Fo,
-                    typename Storage<S>::T *Bo, const typename Storage<S>::C *Tf, typename Storage<S>::C Tconst,
-                    const Geo &g, const StepConst<typename Storage<S>::C> &k, const Codec &cd, unsigned *flag, int slots,
-                    hipStream_t stream, const typename Storage<S>::C *accel = nullptr) {
-    const FusedGeo fg = fused_geometry_t<PcTile>(g, slots);
-    const long long blocks = (long long)fg.tiles_x * fg.tiles_y * fg.nchunks;
-    if (blocks > 2147483647LL) return -1;
-    const dim3 grid((unsigned)blocks), block(PC_THREADS);
-    const bool hask = k.K != 0;
-    auto go = [&](auto H, auto FO) {
-        hipLaunchKernelGGL((k_fused_pc<S, decltype(H)::value, decltype(FO)::value>), grid, block, 0, stream, F, B, Fo,
-                           Bo, Tf, Tconst, g, k, cd, flag, fg, accel);
-    };
-    using tt = std::true_type;
-    using ff = std::false_type;
-    if (accel) hask ? go(tt{}, tt{}) : go(ff{}, tt{});
-    else hask ? go(tt{}, ff{}) : go(ff{}, ff{});
-    return 0;
-}
-
 // Shapes the producer/consumer sweep takes: float and 16-bit storage, more than two z planes
 // (it marches), buffers within the fused sweep's 32-bit offsets.
 inline bool fused_pc_supported(const Geo &g, int storage) {
