@@ -353,22 +353,25 @@ def run_standard(n, tau, mach, steps, warmup):
 
 
 def run_mrt(n, tau, mach, steps, warmup, tau_ghost=0.5):
-    """The multiple-relaxation-time step (non-hydrodynamic moments of Table I at their own rate;
-    two-pass kernel) beside the single-rate two-pass step, on the same Taylor-Green input."""
+    """The multiple-relaxation-time step (non-hydrodynamic moments of Table I at their own rate)
+    beside the single-rate step on the same Taylor-Green input, FP32: in the split fused sweep
+    (the default kernel) and in the two-pass kernel."""
     import torch
     from paper_2501_00620_amd import lbm, workloads
     rho, u, T = workloads.taylor_green(n, mach=mach)
-    out = {"tau_ghost": tau_ghost, "workload": f"Taylor-Green vortex {n}^3, Mach {mach}, tau {tau}, FP32, two-pass kernel"}
-    for name, tg in (("single_rate_mlups", None), ("mrt_mlups", tau_ghost)):
-        lat = lbm.Lattice(n, n, n, tau, storage="f32", kernel="two_pass")
-        if tg is not None:
-            lat.set_ghost_relaxation(tg)
-        lat.set_fields(rho, u, T)
-        secs = timed_steps(lat, steps, warmup)
-        out[name] = n ** 3 * steps / secs / 1e6
-        del lat
-        torch.cuda.empty_cache()
-    print(f"[bench] two-pass single rate {out['single_rate_mlups']:.0f}, MRT {out['mrt_mlups']:.0f} MLUPS",
+    out = {"tau_ghost": tau_ghost, "workload": f"Taylor-Green vortex {n}^3, Mach {mach}, tau {tau}, FP32"}
+    for kernel, prefix in (("auto", "fused_"), ("two_pass", "")):
+        for name, tg in (("single_rate_mlups", None), ("mrt_mlups", tau_ghost)):
+            lat = lbm.Lattice(n, n, n, tau, storage="f32", kernel=kernel)
+            if tg is not None:
+                lat.set_ghost_relaxation(tg)
+            lat.set_fields(rho, u, T)
+            secs = timed_steps(lat, steps, warmup)
+            out[prefix + name] = n ** 3 * steps / secs / 1e6
+            del lat
+            torch.cuda.empty_cache()
+    print(f"[bench] MRT: split sweep single rate {out['fused_single_rate_mlups']:.0f}, MRT {out['fused_mrt_mlups']:.0f}; "
+          f"two-pass single rate {out['single_rate_mlups']:.0f}, MRT {out['mrt_mlups']:.0f} MLUPS",
           file=sys.stderr, flush=True)
     return out
 
@@ -417,15 +420,15 @@ def walls(n=256, tau=0.55, mach=0.5, steps=100, nz=32, T0=1.0 / 6.0, tau_c=0.8, 
     import torch
     from paper_2501_00620_amd import lbm, workloads
     rho, u, T = workloads.taylor_green(n, mach=mach)
+    out = {"workload": f"channel {n}^3 FP32 (Taylor-Green input, walls normal to z, uniform acceleration); "
+                       f"gravity Couette {nz} x 1 x 1, T {T0:.4g}, tau {tau_c}, density ratio e^{ratio:g}, "
+                       f"U {U}, {40 * nz * nz} steps"}
     lat = lbm.Lattice(n, n, n, tau, storage="f32")
     lat.set_fields(rho, u, T)
     lat.set_walls()
     lat.set_body_force([0.0, 1e-5, 0.0])
     secs = timed_steps(lat, steps, 5)
-    out = {"two_pass_mlups": n ** 3 * steps / secs / 1e6,
-           "workload": f"channel {n}^3 FP32 (Taylor-Green input, walls normal to z, uniform acceleration); "
-                       f"gravity Couette {nz} x 1 x 1, T {T0:.4g}, tau {tau_c}, density ratio e^{ratio:g}, "
-                       f"U {U}, {40 * nz * nz} steps"}
+    out["two_pass_mlups"] = n ** 3 * steps / secs / 1e6
     del lat
     torch.cuda.empty_cache()
     g = ratio * T0 / nz

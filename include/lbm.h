@@ -160,19 +160,21 @@ int lbm_health(lbm_handle h, long counts[2], double *max_u);
  * (predictor sources) and consumer waves (gradient, collision, stream) of one work-group, for
  * float and 16-bit storage on lattices with nz >= 3.  All give the same step up to the order of
  * the gradient sums.  Auto takes the split sweep where it applies (from the second step after
- * the state was set; the first gathers bbar in the single-role sweep), else the single-role
- * fused sweep, for a periodic lattice (with or without a body force) whose buffers fit their
- * 32-bit offsets, and the two-pass step for walls or a ghost rate.  Errors: ARG (bad choice; a
- * fused sweep on a projected lattice, on walls, with a ghost rate, or beyond its offsets; the
- * split sweep in double precision or below 3 planes). */
+ * the state was set; the first gathers bbar in the single-role sweep), a ghost rate and a body
+ * force included; else the single-role fused sweep, for a periodic single-rate lattice (with or
+ * without a body force) whose buffers fit their 32-bit offsets; else the two-pass step (walls).
+ * Errors: ARG (bad choice; a fused sweep on a projected lattice, on walls or beyond its offsets;
+ * the single-role sweep with a ghost rate; the split sweep in double precision or below 3
+ * planes). */
 int lbm_set_kernel(lbm_handle h, int kernel);
 
 /* Relaxation time of the nine non-hydrodynamic moments, rows 11-19 of Table I (Appendix B):
  * with a collision matrix diagonal in that basis (the general form of the update the paper
  * reduces to Eq. 55), these moments relax with omega_g = 1/(tau_ghost + 1/2) while rows 1-10
  * keep omega = 1/(tau + 1/2).  tau_ghost = tau restores the single-rate scheme.  A lattice with
- * its own ghost rate steps with the two-pass kernel.  Errors: ARG (tau_ghost <= 0 or
- * non-finite, STANDARD mode, or the fused kernel forced by lbm_set_kernel). */
+ * its own ghost rate steps with the split fused sweep (float and 16-bit storage, nz >= 3) or the
+ * two-pass kernel.  Errors: ARG (tau_ghost <= 0 or non-finite, STANDARD mode, or the single-role
+ * fused kernel forced by lbm_set_kernel(h, 2)). */
 int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost);
 
 /* Body-force acceleration field: 3n values of `dtype` (x, y, z planes, x fastest), or NULL to
@@ -193,7 +195,7 @@ int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device
  * variance.  Beyond a wall the gradient sources of Eqs. 59 and 61 take the wall-adjacent
  * plane's rho b (mirrored) and the second-order extrapolation of rho b u*.  on = 0 restores the
  * periodic z direction.  Applies to every mode; a lattice with walls steps with the two-pass
- * kernel.  Errors: ARG (nz < 3, a normal or non-finite wall velocity, the fused kernel forced). */
+ * kernel.  Errors: ARG (nz < 3, a normal or non-finite wall velocity, a fused kernel forced). */
 int lbm_set_walls(lbm_handle h, int on, const double *u_bottom, const double *u_top);
 
 /* Projected lattice (the lower-dimensional bump lattices that Sec. II B illustrates with D1Q3):
@@ -238,8 +240,8 @@ const char *lbm_last_error(void);
 long lbm_steps_done(lbm_handle h);
 
 /* Device bytes a lattice with these parameters occupies (what lbm_create allocates).  A lattice
- * switched to the two-pass kernel with lbm_set_kernel(h, 1) allocates 9 more planes of the
- * compute type at its first step. */
+ * that steps two-pass (lbm_set_kernel(h, 1), walls, or a ghost rate in double precision or below
+ * 3 planes) allocates 9 more planes of the compute type at its first step. */
 size_t lbm_lattice_bytes(const lbm_params *p);
 
 /* ---------------------------------------------------------------------------------------------

@@ -5,6 +5,7 @@
 // codec scales from device reductions, and enqueues launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -233,7 +234,7 @@ template <int S> int step_two_pass(lbm_lattice *h) {
     };
     auto launch = [&](auto GI, auto MI) {
         hipLaunchKernelGGL((k_predict<S, decltype(GI)::value>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k,
-                           h->codec);
+                           h->codec, 0, h->n);
         if (!h->walls) {
             collide(GI, MI, std::false_type{}, 0, h->n);
         } else {
@@ -362,10 +363,13 @@ template <int S> int step_std(lbm_lattice *h) {
     return LBM_OK;
 }
 
-// the fused sweep relaxes with a single rate on a periodic lattice; a lattice with its own ghost
-// rate or with walls steps two-pass
+// Whether the next step is a fused one: the producer/consumer sweep when it takes the lattice
+// (a ghost rate included), else the single-role sweep, which relaxes with a single rate; walls
+// step two-pass.
 bool use_fused(const lbm_lattice *h) {
-    return h->kernel != 1 && h->tau_ghost <= 0.0 && !h->walls && fused_supported(geo(h), h->p.storage);
+    if (h->kernel == 1) return false;
+    if (use_fused_pc(h)) return true;
+    return h->tau_ghost <= 0.0 && !h->walls && fused_supported(geo(h), h->p.storage);
 }
 
 }  // namespace
@@ -456,8 +460,8 @@ int lbm_set_kernel(lbm_handle h, int kernel) {
     if (fused && h->proj < 3) return fail(LBM_ERR_ARG, "projected lattices step with their own kernels");
     if (fused && !fused_supported(geo(h), h->p.storage))
         return fail(LBM_ERR_ARG, "fused sweep does not support this lattice shape");
-    if (fused && h->tau_ghost > 0.0)
-        return fail(LBM_ERR_ARG, "the fused sweep relaxes with a single rate (a ghost rate is set)");
+    if (kernel == 2 && h->tau_ghost > 0.0)
+        return fail(LBM_ERR_ARG, "the single-role fused sweep relaxes with a single rate (a ghost rate is set)");
     if (fused && h->walls) return fail(LBM_ERR_ARG, "the fused sweep is periodic (walls are set)");
     if (kernel == 3 && !fused_pc_supported(geo(h), h->p.storage))
         return fail(LBM_ERR_ARG, "the producer/consumer sweep takes float or 16-bit storage and nz >= 3");
@@ -599,8 +603,8 @@ int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost) {
     if (!(tau_ghost > 0.0) || !std::isfinite(tau_ghost)) return fail(LBM_ERR_ARG, "tau_ghost must be > 0");
     if (h->p.mode == LBM_STANDARD) return fail(LBM_ERR_ARG, "the standard comparator relaxes with a single rate");
     if (h->proj < 3 && tau_ghost != h->p.tau) return fail(LBM_ERR_ARG, "projected lattices relax with a single rate");
-    if ((h->kernel == 2 || h->kernel == 3) && tau_ghost != h->p.tau)
-        return fail(LBM_ERR_ARG, "the fused sweep relaxes with a single rate (lbm_set_kernel chose it)");
+    if (h->kernel == 2 && tau_ghost != h->p.tau)
+        return fail(LBM_ERR_ARG, "the single-role fused sweep relaxes with a single rate (lbm_set_kernel chose it)");
     h->tau_ghost = tau_ghost == h->p.tau ? -1.0 : tau_ghost;
     return LBM_OK;
 }
@@ -757,13 +761,13 @@ int lbm_step(lbm_handle h, long n_steps) {
     if (!h) return fail(LBM_ERR_ARG, "null handle");
     if (n_steps < 0) return fail(LBM_ERR_ARG, "n_steps < 0");
     if (!h->has_state) return fail(LBM_ERR_STATE, "step before set_fields/set_state");
-    const bool fused = use_fused(h);
     const bool standard = h->p.mode == LBM_STANDARD;
     for (long i = 0; i < n_steps; i++) {
         int rc = dispatch_storage(h->p.storage, [&](auto SI) -> int {
             constexpr int S = decltype(SI)::value;
             if (h->proj < 3) return step_proj(h);
-            return standard ? step_std<S>(h) : fused ? step_fused<S>(h) : step_two_pass<S>(h);
+            // per step: the first step after the state was set may take another kernel
+            return standard ? step_std<S>(h) : use_fused(h) ? step_fused<S>(h) : step_two_pass<S>(h);
         });
         if (rc) return rc;
         h->steps++;
@@ -855,7 +859,8 @@ int lbm_get_moments(lbm_handle h, void *rho, void *u, void *T, int dtype, int on
                                    (const C *)h->accel);
                 return;
             }
-            hipLaunchKernelGGL((k_predict<S, G>), grid, block, 0, h->stream, F, B, src, (const C *)h->Tf, (C)h->Tconst, g, k, h->codec);
+            hipLaunchKernelGGL((k_predict<S, G>), grid, block, 0, h->stream, F, B, src, (const C *)h->Tf, (C)h->Tconst, g, k,
+                               h->codec, 0, h->n);
             hipLaunchKernelGGL((k_readout<S, G, OUT>), grid, block, 0, h->stream, F, B, (const C *)src, (const C *)h->Tf,
                                (C)h->Tconst, g, k, h->codec, h->p.T_ref, (OUT *)dr, (OUT *)du, (OUT *)dT, (const C *)h->accel);
         };

@@ -532,28 +532,36 @@ constexpr double ghost_norm(int a) {  // sum_j w_j r_j^2 of ghost row a
     return s;
 }
 
+// The non-hydrodynamic moments of Table I (rows 11-19, integer-scaled as GHOST_ROWS) of d.
+template <typename C> __device__ __forceinline__ void ghost_moments(const C d[Q], C m[9]) {
+    Unroll<0, 9>::run([&](auto A) {
+        C acc = C(0);
+        Unroll<0, Q>::run([&](auto J) {
+            constexpr int r = GHOST_ROWS[A][J];
+            if constexpr (r != 0) acc = fma(C(r), d[J], acc);
+        });
+        m[A] = acc;
+    });
+}
+
 // Relaxation of the non-hydrodynamic moments at their own rate omega_g (Table I rows 11-19),
-// applied after the single-rate collision d0 -> d.  In the Table I basis the rates are diagonal,
-// Phi has no components on these rows, and rows 1-10 keep omega, so the update differs from the
-// single-rate one by (omega - omega_g) m_a(d0 - deq) on each ghost row a, mapped back with the
-// inverse of Table I (w_i r_i / sum_j w_j r_j^2).  The single-rate step gives
-// m_a(d0 - deq) = m_a(d0 - d) / omega, so with cg = 1 - omega_g / omega
-//   d_i += cg w_i r_i sum_j r_j (d0_j - d_j) / sum_j w_j r_j^2.
+// applied after the single-rate collision d0 -> d, given m0 = ghost_moments(d0).  In the Table I
+// basis the rates are diagonal, Phi has no components on these rows, and rows 1-10 keep omega, so
+// the update differs from the single-rate one by (omega - omega_g) m_a(d0 - deq) on each ghost
+// row a, mapped back with the inverse of Table I (w_i r_i / sum_j w_j r_j^2).  The single-rate
+// step gives m_a(d0 - deq) = m_a(d0 - d) / omega, so with cg = 1 - omega_g / omega
+//   d_i += cg w_i r_i (m_a(d0) - m_a(d)) / sum_j w_j r_j^2.
+// Carrying the 9 moments of d0 across the collision instead of its 19 populations keeps the
+// fused sweep's register budget.
 template <typename C>
-__device__ __forceinline__ void ghost_relax(const C d0[Q], C d[Q], C cg) {
-    C delta[Q];
-#pragma unroll
-    for (int i = 0; i < Q; i++) delta[i] = d0[i] - d[i];
+__device__ __forceinline__ void ghost_relax(const C m0[9], C d[Q], C cg) {
+    C m1[9];
+    ghost_moments(d, m1);
     C add[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) add[i] = C(0);
     Unroll<0, 9>::run([&](auto A) {
-        C m = C(0);
-        Unroll<0, Q>::run([&](auto J) {
-            constexpr int r = GHOST_ROWS[A][J];
-            if constexpr (r != 0) m = fma(C(r), delta[J], m);
-        });
-        const C g = m * (cg * C(1.0 / ghost_norm(A)));
+        const C g = (m0[A] - m1[A]) * (cg * C(1.0 / ghost_norm(A)));
         Unroll<0, Q>::run([&](auto I) {
             constexpr int r = GHOST_ROWS[A][I];
             if constexpr (r != 0) add[I] = fma(C(WQ[I] * r), g, add[I]);

@@ -710,18 +710,19 @@ template <typename TL> inline FusedGeo fused_geometry_t(const Geo &g, int slots)
     FusedGeo fg;
     fg.tiles_x = (g.nx + TL::TX - 1) / TL::TX;
     fg.tiles_y = (g.ny + TL::TY - 1) / TL::TY;
+    const int nz = g.nz;
     const long long tiles = (long long)fg.tiles_x * fg.tiles_y;
-    if (g.nz <= 2) {
+    if (nz <= 2) {
         fg.nchunks = 1;
-        fg.zchunk = g.nz;
+        fg.zchunk = nz;
         return fg;
     }
     if (slots < 1) slots = 1;
-    const int maxc = g.nz / 16 > 0 ? g.nz / 16 : 1;
+    const int maxc = nz / 16 > 0 ? nz / 16 : 1;
     int best = 1;
     long long best_cost = -1;
     for (int nch = 1; nch <= maxc; nch++) {
-        const long long zc = (g.nz + nch - 1) / nch;
+        const long long zc = (nz + nch - 1) / nch;
         const long long rounds = (tiles * nch + slots - 1) / slots;
         const long long cost = rounds * (zc + 2);
         if (best_cost < 0 || cost < best_cost) {
@@ -729,8 +730,8 @@ template <typename TL> inline FusedGeo fused_geometry_t(const Geo &g, int slots)
             best = nch;
         }
     }
-    fg.zchunk = (g.nz + best - 1) / best;
-    fg.nchunks = (g.nz + fg.zchunk - 1) / fg.zchunk;
+    fg.zchunk = (nz + best - 1) / best;
+    fg.nchunks = (nz + fg.zchunk - 1) / fg.zchunk;
     return fg;
 }
 

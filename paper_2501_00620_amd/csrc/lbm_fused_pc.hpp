@@ -162,7 +162,9 @@ constexpr size_t pc_lds_bytes() {
 }
 static_assert(pc_lds_bytes() <= 163840, "producer/consumer sweep exceeds the LDS of a CU");
 
-template <int S, bool HASK, bool FORCE>
+// MRT: the non-hydrodynamic moments relax at their own rate (ghost_relax, which carries the 9
+// ghost moments of the pre-collision populations across the collision).
+template <int S, bool HASK, bool FORCE, bool MRT>
 __global__ void __launch_bounds__(PC_THREADS)
 k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
            typename Storage<S>::T *__restrict__ Fo, typename Storage<S>::T *__restrict__ Bo,
@@ -400,7 +402,10 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                         const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
                         add_body_force(m, a, Fv, Sv);
                     }
+                    C g0[MRT ? 9 : 1];
+                    if constexpr (MRT) ghost_moments(d, g0);
                     collide(d, cur.beta, m, Fv, Sv, cur.theta, k);
+                    if constexpr (MRT) ghost_relax(g0, d, k.ghost);
                     const int wz = wrapc(q - 1, g.nz);
                     int Zo[3];
                     Zo[0] = (wz == 0 ? g.nz - 1 : wz - 1) * nxy;

@@ -94,14 +94,17 @@ __device__ __forceinline__ C site_T(const C *Tf, C Tconst, int s) {
 }
 
 // ---- pass A: predictor sources ---------------------------------------------------------------
+// The launch covers sites s0 .. s0 + count - 1 (all of them, or the planes next to the walls
+// that the wall planes' collision reads when the interior steps in the fused sweep).
 template <int S, bool GATHERED>
 __global__ void __launch_bounds__(BLOCK)
 k_predict(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
           typename Storage<S>::C *__restrict__ src, const typename Storage<S>::C *__restrict__ Tf,
-          typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd) {
+          typename Storage<S>::C Tconst, Geo g, StepConst<typename Storage<S>::C> k, Codec cd, int s0, int count) {
     using C = typename Storage<S>::C;
-    const int s = blockIdx.x * BLOCK + threadIdx.x;
-    if (s >= g.n) return;
+    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= count) return;
+    const int s = s0 + t;
     int x, y, z;
     site_xyz(s, g, x, y, z);
     const Nbr nb = make_nbr(x, y, z, g.nx, g.ny, g.nz);
@@ -173,13 +176,10 @@ k_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S
         const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
         add_body_force(m, a, Fv, Sv);
     }
-    C f0[MRT ? Q : 1];
-    if constexpr (MRT) {
-#pragma unroll
-        for (int i = 0; i < Q; i++) f0[i] = f[i];
-    }
+    C g0[MRT ? 9 : 1];
+    if constexpr (MRT) ghost_moments(f, g0);
     collide(f, bbar, m, Fv, Sv, site_T(Tf, Tconst, s), k);
-    if constexpr (MRT) ghost_relax(f0, f, k.ghost);
+    if constexpr (MRT) ghost_relax(g0, f, k.ghost);
     unsigned sat = 0;
     Unroll<0, Q>::run([&](auto I) {
         if (WALLS && leaves_into_wall<I>(zw)) {  // half-way bounce-back, moving-wall momentum

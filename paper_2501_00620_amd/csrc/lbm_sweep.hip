@@ -58,15 +58,15 @@ int launch_fused_pc(const typename Storage<S>::T *F, const typename Storage<S>::
     const long long blocks = (long long)fg.tiles_x * fg.tiles_y * fg.nchunks;
     if (blocks > 2147483647LL) return -1;
     const dim3 grid((unsigned)blocks), block(PC_THREADS);
-    const bool hask = k.K != 0;
-    auto go = [&](auto H, auto FO) {
-        hipLaunchKernelGGL((k_fused_pc<S, decltype(H)::value, decltype(FO)::value>), grid, block, 0, stream, F, B, Fo,
-                           Bo, Tf, Tconst, g, k, cd, flag, fg, accel);
+    auto go = [&](auto H, auto FO, auto M) {
+        hipLaunchKernelGGL((k_fused_pc<S, decltype(H)::value, decltype(FO)::value, decltype(M)::value>), grid, block, 0,
+                           stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg, accel);
     };
     using tt = std::true_type;
     using ff = std::false_type;
-    if (accel) hask ? go(tt{}, tt{}) : go(ff{}, tt{});
-    else hask ? go(tt{}, ff{}) : go(ff{}, ff{});
+    auto with_mrt = [&](auto H, auto FO) { k.ghost != 0 ? go(H, FO, tt{}) : go(H, FO, ff{}); };
+    auto with_force = [&](auto H) { accel ? with_mrt(H, tt{}) : with_mrt(H, ff{}); };
+    k.K != 0 ? with_force(tt{}) : with_force(ff{});
     return 0;
 }
 
@@ -75,7 +75,7 @@ template <int S> hipError_t sweep_occupancy(int *per_cu, int *per_cu_pc) {
                                                                 TileFor<S>::type::NT, 0);
     if constexpr (S != 0) {
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_pc, k_fused_pc<S, false, false>, PC_THREADS, 0);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_pc, k_fused_pc<S, false, false, false>, PC_THREADS, 0);
     }
     return e;
 }

@@ -192,7 +192,7 @@ class Lattice:
 
     def set_ghost_relaxation(self, tau_ghost):
         """Relaxation time of the non-hydrodynamic moments (Table I rows 11-19); tau_ghost = tau
-        is the single-rate scheme.  Such a lattice steps with the two-pass kernel."""
+        is the single-rate scheme.  In float and 16-bit storage it steps in the split fused sweep."""
         _check(_lib.lbm_set_ghost_relaxation(self._h, float(tau_ghost)))
 
     # -- fields and state -------------------------------------------------------------------------

@@ -33,11 +33,13 @@ UB, UT = [0.02, -0.01, 0.0], [-0.015, 0.03, 0.0]
 @pytest.mark.parametrize("dims", [(17, 9, 5), (32, 16, 3), (8, 6, 7)])
 @pytest.mark.parametrize("mode", ["thermal", "iso", "standard"])
 @pytest.mark.parametrize("force", [False, True])
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
-def test_walls_parity(dims, mode, force, storage, tol):
+@pytest.mark.parametrize("storage,tol,kernel", [("f64", 1e-12, "auto"), ("f32", 1e-5, "auto"),
+                                                ("f32", 1e-5, "two_pass")])
+def test_walls_parity(dims, mode, force, storage, tol, kernel):
+    # a lattice with walls steps two-pass whatever kernel "auto" would take without them
     tau, steps = 0.7, 30
     fields = wl.fourier_fields(*dims, seed=31, u_max=0.2)
-    g = lbm().Lattice(*dims, tau, storage=storage, mode=mode)
+    g = lbm().Lattice(*dims, tau, storage=storage, mode=mode, kernel=kernel)
     g.set_fields(*fields)
     g.set_walls(UB, UT)
     o = oracle.OracleLattice(*dims, tau, mode=mode)
@@ -172,3 +174,50 @@ def test_wall_argument_errors():
     f = L.Lattice(8, 8, 8, 0.7, storage="f32", kernel="fused")
     with pytest.raises(L.LBMError):
         f.set_walls()
+
+
+@pytest.mark.skip(reason="walls in the split fused sweep are switched off: its wall variant faulted the "
+                         "GPU (memory aperture violation) in its first run, cause not established")
+@pytest.mark.parametrize("dims", [(17, 9, 5), (32, 16, 3), (70, 13, 37)])
+@pytest.mark.parametrize("tau_g", [None, 0.5])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16dev", 1e-3), ("bf16dev", 1e-2)])
+def test_split_sweep_with_walls_equals_two_pass(dims, tau_g, storage, tol):
+    # Moving walls, a body force and (or not) a ghost rate: the split sweep with the wall planes
+    # apart against the two-pass step, in every storage it takes.  The same arithmetic up to the
+    # order of the gradient sums (the bars of the periodic comparison).  nz = 37 sweeps the 35
+    # interior planes in two z chunks; nz = 3 leaves one interior plane.
+    fields = wl.fourier_fields(*dims, seed=41, u_max=0.2)
+    _, a, _ = wl.fourier_fields(*dims, seed=42, u_max=1.0)
+    a = 2e-4 * a + np.array([0.0, 0.0, -1e-3]).reshape(3, 1, 1, 1)
+    out = []
+    for kernel in ("two_pass", "fused_pc"):
+        g = lbm().Lattice(*dims, 0.7, storage=storage, kernel=kernel)
+        g.set_fields(*fields)
+        g.set_walls(UB, UT)
+        g.set_body_force(a)
+        if tau_g is not None:
+            g.set_ghost_relaxation(tau_g)
+        g.step(9)
+        assert g.health()[:2] == (0, 0)
+        F, b = g.get_state()
+        out.append((F.cpu().numpy(), b.cpu().numpy()))
+    assert rel_l2(out[1][0], out[0][0]) <= tol, rel_l2(out[1][0], out[0][0])
+    assert rel_l2(out[1][1], out[0][1]) <= tol, rel_l2(out[1][1], out[0][1])
+
+
+@pytest.mark.skip(reason="walls in the split fused sweep are switched off: its wall variant faulted the "
+                         "GPU (memory aperture violation) in its first run, cause not established")
+def test_split_sweep_wall_channel_mass_and_couette():
+    # FP32 Couette channel in the split sweep: exact mass conservation with walls at rest, and the
+    # steady linear profile between a wall at rest and one moving at U (the two-pass bar)
+    L = lbm()
+    nz, U, T0 = 12, 0.02, 0.25
+    g = L.Lattice(4, 4, nz, 0.8, storage="f32", mode="iso", kernel="fused_pc")
+    g.set_fields(np.ones((nz, 4, 4)), np.zeros((3, nz, 4, 4)), np.full((nz, 4, 4), T0))
+    g.set_walls([0, 0, 0], [U, 0, 0])
+    m0 = g.get_state()[0].sum().item()
+    g.step(6000)
+    assert abs(g.get_state()[0].sum().item() / m0 - 1) < 1e-6
+    u = g.moments()[1][0].cpu().numpy().mean(axis=(1, 2))
+    z = np.arange(nz) + 0.5
+    assert np.abs(u - U * z / nz).max() <= 1e-3 * U, u - U * z / nz
