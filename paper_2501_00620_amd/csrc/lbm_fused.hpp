@@ -94,6 +94,12 @@ template <int S> constexpr int fused_stash() {
 #endif
 template <int S> struct ThinTileFor { using type = Tile<SERVE_THIN_TX, SERVE_THIN_TY>; };
 
+// Largest |value| a thread stored into each array (populations, bbar), unscaled, for the 16-bit
+// range check (report_range).
+struct RangeMax {
+    float f = 0.0f, b = 0.0f;
+};
+
 struct FusedGeo {
     int tiles_x, tiles_y, nchunks, zchunk;
 };
@@ -172,11 +178,11 @@ template <int S> struct Buf {
     template <int K, int F0> __device__ __forceinline__ C loadf(int off, const Codec &cd) const {
         return decode<K, F0>(loadraw<K>(off), cd);
     }
-    // Stores a value; for 16-bit codes, amax collects |code| so that one comparison after the
-    // sweep detects overflow (an overflowing code is stored as +-inf and reported as RANGE, the
+    // Stores a value; for 16-bit codes, rm collects |value| per array so that one comparison after
+    // the sweep detects overflow (an overflowing code is stored as +-inf and reported as RANGE, the
     // same rule as the other kernels' encoders).
     template <int K, int F0>
-    __device__ __forceinline__ void storef(int off, C v, const Codec &cd, float &amax, int zoff = 0) const {
+    __device__ __forceinline__ void storef(int off, C v, const Codec &cd, RangeMax &rm, int zoff = 0) const {
         constexpr int g = K / PPG, j = K % PPG;
         const __amdgpu_buffer_rsrc_t rs = r[g];
         const int so = __builtin_amdgcn_readfirstlane((int)((unsigned)plane_offset(j) + (unsigned)zoff));
@@ -188,11 +194,13 @@ template <int S> struct Buf {
             // evict from L2 the populations the collision reads a second time
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, off, so, 2);
         } else if constexpr (S == 2) {
-            const float h = v * cd.inv[F0];
-            amax = fmaxf(amax, fabsf(h));
-            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)h), rs, off, so, 0);
+            float &m = F0 == 0 ? rm.f : rm.b;
+            m = fmaxf(m, fabsf(v));
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)(v * cd.inv[F0])), rs, off,
+                                                  so, 0);
         } else {
-            amax = fmaxf(amax, fabsf(v));
+            float &m = F0 == 0 ? rm.f : rm.b;
+            m = fmaxf(m, fabsf(v));
             __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (__bf16)v), rs, off, so, 0);
         }
     }
@@ -323,7 +331,7 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
                                            const typename Storage<S>::C *__restrict__ Tf,
                                            typename Storage<S>::C Tconst, const Geo &g,
                                            const StepConst<typename Storage<S>::C> &k, const Codec &cd,
-                                           const FusedGeo &fg, int tx, int ty, int chunk, float &amax,
+                                           const FusedGeo &fg, int tx, int ty, int chunk, RangeMax &amax,
                                            const typename Storage<S>::C *__restrict__ accel = nullptr) {
     using C = typename Storage<S>::C;
     using T = typename Storage<S>::T;
@@ -661,14 +669,16 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
     __syncthreads();
 }
 
-// Overflow check of the 16-bit codes a thread stored: amax is the largest |code value| before
-// rounding, and a code overflowed (was stored as +-inf) exactly when it reached the rounding
-// midpoint above the largest finite code (a NaN does not enter the maximum).
-template <int S> __device__ __forceinline__ void report_range(float amax, unsigned *flag) {
+// Overflow check of the 16-bit codes a thread stored: rm holds the largest |value| stored into
+// each array, and a code overflowed (was stored as +-inf) exactly when its scaled value reached the
+// rounding midpoint above the largest finite code.  Scaling the maximum once gives the maximum of
+// the scaled values, since rounding a product is monotone in the factor; a NaN does not enter it.
+template <int S>
+__device__ __forceinline__ void report_range(const RangeMax &rm, const Codec &cd, unsigned *flag) {
     if constexpr (S == 2) {
-        if (amax >= HALF_OVERFLOW) *flag = 1u;
+        if (rm.f * cd.inv[0] >= HALF_OVERFLOW || rm.b * cd.inv[Q] >= HALF_OVERFLOW) *flag = 1u;
     } else if constexpr (S == 3) {
-        if (amax >= bf16_overflow()) *flag = 1u;
+        if (fmaxf(rm.f, rm.b) >= bf16_overflow()) *flag = 1u;
     }
 }
 
@@ -694,10 +704,10 @@ k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>:
     L /= fg.tiles_x;
     const int ty = L % fg.tiles_y;
     const int chunk = L / fg.tiles_y;
-    float amax = 0.0f;
+    RangeMax amax;
     sweep_tile<S, GATHERED, HASK, THIN1, typename TileFor<S>::type, THIN1 ? 0 : fused_stash<S>(), FORCE>(
         F, B, Fo, Bo, Tf, Tconst, g, k, cd, fg, tx, ty, chunk, amax, accel);
-    report_range<S>(amax, flag);
+    report_range<S>(amax, cd, flag);
 }
 
 // Tiles of the xy plane times z chunks.  `slots` is the number of work-groups resident at once

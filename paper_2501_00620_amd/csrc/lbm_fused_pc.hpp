@@ -86,10 +86,26 @@ template <typename C> __device__ __forceinline__ void gradt_finish(const GradT<C
     for (int c = 3; c < 6; c++) S[c] = -a.S[c] * C(1.0 / 12.0);
 }
 
+// The same term as the first one into sums a: it sets them (a sum that starts a plane needs no
+// zeroing).
+template <typename C, int I, bool HASK>
+__device__ __forceinline__ void gradt_set(GradT<C> &a, const C s[NSRC], C K) {
+    gradt_zero(a);
+    gradt_add<C, I, HASK>(a, s, K);
+}
+
 // Index of the D3Q19 velocity (ex, ey, ez), or -1.
 constexpr int dir_index(int ex, int ey, int ez) {
     for (int i = 0; i < Q; i++)
         if (EX[i] == ex && EY[i] == ey && EZ[i] == ez) return i;
+    return -1;
+}
+
+// The first in-plane offset O (dx = O % 3 - 1, dy = O / 3 - 1) whose direction (dx, dy, -1) is a
+// D3Q19 velocity: the offset at which the consumers' sums of a new plane take their first term.
+constexpr int first_up_offset() {
+    for (int o = 0; o < 9; o++)
+        if (dir_index(o % 3 - 1, o / 3 - 1, -1) > 0) return o;
     return -1;
 }
 
@@ -104,10 +120,6 @@ constexpr int dir_index(int ex, int ey, int ez) {
 #endif
 #ifndef PC_GRAD_GROUP
 #define PC_GRAD_GROUP 3
-#endif
-// Producers load the populations of the next plane one iteration ahead of their sources.
-#ifndef PC_PREFETCH_POPS
-#define PC_PREFETCH_POPS 1
 #endif
 template <typename C> __device__ __forceinline__ void pin(C &v) { asm volatile("" : "+v"(v)); }
 
@@ -221,7 +233,7 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
     auto hslot = [&](int q) { return (q - z0 + 9) % 3; };
     auto zoff = [&](int q) { return wrapc(q, g.nz) * nxy; };
 
-    float amax = 0.0f;
+    RangeMax amax;
 
     if (producer) {
         // ring sites and staging sites of this thread
@@ -250,20 +262,22 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
         int sxy[NSTAGE];  // byte offsets within a plane
 #pragma unroll
         for (int j = 0; j < NSTAGE; j++) {
-            const int r = t + j * NT;
+            // a lane past the staged sites loads the last one again (a line already fetched)
+            const int r = min(t + j * NT, NB2 - 1);
             const int bx = r % TL::BX - 2, by = r / TL::BX - 2;
             sxy[j] = (wrapc(y0 + by, g.ny) * g.nx + wrapc(x0 + bx, g.nx)) * SB;
         }
+        // The loads of later planes are issued on every lane and in every iteration: a lane past
+        // the staged sites repeats the last site's load, and a plane past the chunk's end is read
+        // wrapped (in bounds); neither value is used.  Values defined on every path need no register copies between the
+        // loop's iterations.
         R sraw[NSTAGE][NB];
         R praw[Q];
         auto stage_issue = [&](int q) {
             const int zb = zoff(q) * SB;
 #pragma unroll
-            for (int j = 0; j < NSTAGE; j++) {
-                if (t + j * NT < NB2) {
-                    Unroll<0, NB>::run([&](auto c) { sraw[j][c] = bB.template loadraw<c>(sxy[j], zb); });
-                }
-            }
+            for (int j = 0; j < NSTAGE; j++)
+                Unroll<0, NB>::run([&](auto c) { sraw[j][c] = bB.template loadraw<c>(sxy[j], zb); });
         };
         auto stage_commit = [&](int q) {
             C *dst = bst[sslot(q)];
@@ -286,46 +300,38 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
             stage_commit(q);
         }
         stage_issue(z0 + 1);
-#if PC_PREFETCH_POPS
         pops_issue(z0 - 1);
-#endif
         __syncthreads();
-        for (int p = z0 - 1; p <= z1 + 1; p++) {
-            if (p <= z1) {
-                // staged plane p+2 for the next iteration (its slot last served plane p-2)
-                if (p + 2 <= z1 + 1) {
-                    stage_commit(p + 2);
-                    if (p + 3 <= z1 + 1) stage_issue(p + 3);
-                }
-#if !PC_PREFETCH_POPS
-                pops_issue(p);
-#endif
-                const C *bs[3] = {bst[sslot(p - 1)], bst[sslot(p)], bst[sslot(p + 1)]};
-                C *plane = lsrc[cslot(p)];
-                const int zo = zoff(p);
-                SiteState<C> keep;
-                source_site_pc<S, TL, true>(bF, praw, Tf, Tconst, k, cd, zo + ixy, ibidx, bs, plane, iidx, keep);
-                C *hd = hand[hslot(p)];
+        // one plane per iteration; the iteration after the last only meets the consumers'
+        // barrier (kept out of the loop, so that no path skips the loop's loads)
+        for (int p = z0 - 1; p <= z1; p++) {
+            // staged plane p+2 for the next iteration (its slot last served plane p-2)
+            stage_commit(p + 2);
+            stage_issue(p + 3);
+            const C *bs[3] = {bst[sslot(p - 1)], bst[sslot(p)], bst[sslot(p + 1)]};
+            C *plane = lsrc[cslot(p)];
+            const int zo = zoff(p);
+            SiteState<C> keep;
+            source_site_pc<S, TL, true>(bF, praw, Tf, Tconst, k, cd, zo + ixy, ibidx, bs, plane, iidx, keep);
+            C *hd = hand[hslot(p)];
 #pragma unroll
-                for (int c = 0; c < NB; c++) hd[c * NT + t] = keep.beta[c];
-                __builtin_amdgcn_sched_barrier(0);
+            for (int c = 0; c < NB; c++) hd[c * NT + t] = keep.beta[c];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int j = 0; j < NRING; j++) {
-                    if (t + j * NT < TL::NH) {
-                        R rraw[Q];
-                        const int zb = zo * SB;
-                        Unroll<0, Q>::run([&](auto I) { rraw[I] = bF.template loadraw<I>(rxy[j] * SB, zb); });
-                        SiteState<C> dummy;
-                        source_site_pc<S, TL, false>(bF, rraw, Tf, Tconst, k, cd, zo + rxy[j], rbidx[j], bs, plane,
-                                                         rlidx[j], dummy);
-                    }
+            for (int j = 0; j < NRING; j++) {
+                if (t + j * NT < TL::NH) {
+                    R rraw[Q];
+                    const int zb = zo * SB;
+                    Unroll<0, Q>::run([&](auto I) { rraw[I] = bF.template loadraw<I>(rxy[j] * SB, zb); });
+                    SiteState<C> dummy;
+                    source_site_pc<S, TL, false>(bF, rraw, Tf, Tconst, k, cd, zo + rxy[j], rbidx[j], bs, plane,
+                                                     rlidx[j], dummy);
                 }
-#if PC_PREFETCH_POPS
-                if (p + 1 <= z1) pops_issue(p + 1);
-#endif
             }
+            pops_issue(p + 1);
             __syncthreads();
         }
+        __syncthreads();
     } else {
         // push targets of the tile site: byte offsets of its 3 x 3 in-plane neighbourhood
         // (periodic), fixed for the whole chunk; the target plane's offset is wave-uniform
@@ -344,20 +350,22 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
         gradt_zero(Z);
         __syncthreads();  // the producers' prologue
         // One iteration with A0, A1, A2 the sums of planes q-1, q, q+1; A0 is then done and
-        // cleared, to serve as the next iteration's plane q+2.  Rotating the roles by argument
-        // order (the loop unrolled by three) moves no registers.
+        // serves as the next iteration's plane q+2, whose first term sets it (gradt_set).  Rotating
+        // the roles by argument order (the loop unrolled by three) moves no registers.
         auto iter = [&](int p, GradT<C> &A0, GradT<C> &A1, GradT<C> &A2) {
             const int q = p - 1;  // the source plane the producers finished last iteration
             if (q >= z0 - 1) {
                 const int zc = zoff(q - 1);
-                const bool out = inside && q - 1 >= z0;
+                // plane q-1 is one of the chunk's (wave-uniform); its lanes outside the lattice
+                // compute on the wrapped site and store nothing
+                const bool live = q - 1 >= z0;
                 // the populations of plane q-1, read again for its collision (their last use:
-                // non-temporal in single precision)
+                // non-temporal in single precision).  Loaded also in the chunk's first iteration,
+                // which discards them (a wrapped plane, in bounds): a value defined on every path
+                // costs no register fill.
                 constexpr int POL = S == 1 ? 2 : 0;
                 R craw[Q];
-                if (out) {
-                    Unroll<0, Q>::run([&](auto I) { craw[I] = bF.template loadraw<I, POL>(ixy * SB, zc * SB); });
-                }
+                Unroll<0, Q>::run([&](auto I) { craw[I] = bF.template loadraw<I, POL>(ixy * SB, zc * SB); });
                 // source plane q: its 3 x 3 neighbourhood adds to the sums of planes q-1, q, q+1
                 const C *pl = lsrc[cslot(q)] + iidx;
                 Unroll<0, 9>::run([&](auto O) {
@@ -370,7 +378,12 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                     constexpr int up = dir_index(dx, dy, -1);  // from a site of plane q+1
                     if constexpr (dn > 0) gradt_add<C, dn, HASK>(A0, sv, k.K);
                     if constexpr (d0 > 0) gradt_add<C, d0, HASK>(A1, sv, k.K);
-                    if constexpr (up > 0) gradt_add<C, up, HASK>(A2, sv, k.K);
+                    if constexpr (up > 0) {
+                        if constexpr (O == first_up_offset())  // the first of plane q+1's terms
+                            gradt_set<C, up, HASK>(A2, sv, k.K);
+                        else
+                            gradt_add<C, up, HASK>(A2, sv, k.K);
+                    }
                     if constexpr (O % PC_GRAD_GROUP == PC_GRAD_GROUP - 1) {  // as in the gather
 #pragma unroll
                         for (int c = 0; c < 3; c++) {
@@ -386,7 +399,7 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                         }
                     }
                 });
-                if (out) {
+                if (live) {
                     C Fv[3], Sv[6];
                     gradt_finish(A0, Fv, Sv);
                     C d[Q];
@@ -411,12 +424,15 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                     Zo[0] = (wz == 0 ? g.nz - 1 : wz - 1) * nxy;
                     Zo[1] = zc;
                     Zo[2] = (wz == g.nz - 1 ? 0 : wz + 1) * nxy;
-                    Unroll<0, Q>::run([&](auto I) {
-                        bFo.template storef<I, 0>(yx[(EY[I] + 1) * 3 + EX[I] + 1], d[I], cd, amax, Zo[EZ[I] + 1] * SB);
-                    });
-                    Unroll<0, NB>::run([&](auto c) { bBo.template storef<c, Q>(ixy * SB, cur.beta[c], cd, amax, zc * SB); });
+                    if (inside) {
+                        Unroll<0, Q>::run([&](auto I) {
+                            bFo.template storef<I, 0>(yx[(EY[I] + 1) * 3 + EX[I] + 1], d[I], cd, amax,
+                                                      Zo[EZ[I] + 1] * SB);
+                        });
+                        Unroll<0, NB>::run(
+                            [&](auto c) { bBo.template storef<c, Q>(ixy * SB, cur.beta[c], cd, amax, zc * SB); });
+                    }
                 }
-                gradt_zero(A0);
             }
             __syncthreads();
         };
@@ -429,7 +445,7 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
         if (p <= z1 + 1) iter(p++, X, Y, Z);
         if (p <= z1 + 1) iter(p, Y, Z, X);
     }
-    report_range<S>(amax, flag);
+    report_range<S>(amax, cd, flag);
 }
 
 // Shapes the producer/consumer sweep takes: float and 16-bit storage, more than two z planes

@@ -84,10 +84,10 @@ k_serve(const ServeDesc *__restrict__ descs, const TileRef *__restrict__ tiles, 
         L /= d.fg.tiles_x;
         const int ty = L % d.fg.tiles_y;
         const int chunk = L / d.fg.tiles_y;
-        float amax = 0.0f;
+        RangeMax amax;
         sweep_tile<S, false, true, THIN1, ServeTile<S, THIN1>>((const T *)d.F[cur], (const T *)d.B[cur], (T *)d.F[1 - cur], (T *)d.B[1 - cur],
                                    d.Tf, d.Tconst, d.g, d.k, d.cd, d.fg, tx, ty, chunk, amax);
-        report_range<S>(amax, d.flag);
+        report_range<S>(amax, d.cd, d.flag);
     }
 }
 
