@@ -268,8 +268,8 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
             sxy[j] = (wrapc(y0 + by, g.ny) * g.nx + wrapc(x0 + bx, g.nx)) * SB;
         }
         // The loads of later planes are issued on every lane and in every iteration: a lane past
-        // the staged sites repeats the last site's load, and a plane past the chunk's end is read
-        // wrapped (in bounds); neither value is used.  Values defined on every path need no register copies between the
+        // the staged sites repeats the last site's load, and past the chunk's end the last plane
+        // it needs is read again (an L2 hit); neither value is used.  Values defined on every path need no register copies between the
         // loop's iterations.
         R sraw[NSTAGE][NB];
         R praw[Q];
@@ -307,7 +307,7 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
         for (int p = z0 - 1; p <= z1; p++) {
             // staged plane p+2 for the next iteration (its slot last served plane p-2)
             stage_commit(p + 2);
-            stage_issue(p + 3);
+            stage_issue(min(p + 3, z1 + 1));
             const C *bs[3] = {bst[sslot(p - 1)], bst[sslot(p)], bst[sslot(p + 1)]};
             C *plane = lsrc[cslot(p)];
             const int zo = zoff(p);
@@ -328,7 +328,7 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                                                      rlidx[j], dummy);
                 }
             }
-            pops_issue(p + 1);
+            pops_issue(min(p + 1, z1));
             __syncthreads();
         }
         __syncthreads();
@@ -360,12 +360,13 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                 // compute on the wrapped site and store nothing
                 const bool live = q - 1 >= z0;
                 // the populations of plane q-1, read again for its collision (their last use:
-                // non-temporal in single precision).  Loaded also in the chunk's first iteration,
-                // which discards them (a wrapped plane, in bounds): a value defined on every path
-                // costs no register fill.
+                // non-temporal in single precision).  The chunk's first iteration, which has no
+                // plane to collide, loads the plane the producers read first (an L2 hit) and
+                // discards it: a value defined on every path costs no register fill.
                 constexpr int POL = S == 1 ? 2 : 0;
+                const int zl = live ? zc : zoff(z0 - 1);
                 R craw[Q];
-                Unroll<0, Q>::run([&](auto I) { craw[I] = bF.template loadraw<I, POL>(ixy * SB, zc * SB); });
+                Unroll<0, Q>::run([&](auto I) { craw[I] = bF.template loadraw<I, POL>(ixy * SB, zl * SB); });
                 // source plane q: its 3 x 3 neighbourhood adds to the sums of planes q-1, q, q+1
                 const C *pl = lsrc[cslot(q)] + iidx;
                 Unroll<0, 9>::run([&](auto O) {
