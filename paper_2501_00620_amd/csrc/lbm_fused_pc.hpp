@@ -259,34 +259,35 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
             rlidx[j] = (rly + 1) * TL::HX + (rlx + 1);
             rbidx[j] = (rly + 2) * TL::BX + (rlx + 2);
         }
+        // Staged sites: every thread takes one (site t) and the last NB2 - NT threads a second
+        // (site t + NT - SHIFT), so that the waves holding ring sites (the first NH threads) stage
+        // one site and the others two.  A wave with any second site loads for all its lanes (a
+        // lane without one repeats site NT, a line already fetched); the others skip the round.
+        static_assert(NSTAGE == 2 && TL::NH <= (2 * NT - NB2) / 64 * 64, "staging rounds of the producer tile");
+        constexpr int SHIFT = 2 * NT - NB2;
+        const bool stage2 = __builtin_amdgcn_readfirstlane(t >> 6) >= SHIFT / 64;  // wave-uniform
         int sxy[NSTAGE];  // byte offsets within a plane
 #pragma unroll
         for (int j = 0; j < NSTAGE; j++) {
-            // a lane past the staged sites loads the last one again (a line already fetched)
-            const int r = min(t + j * NT, NB2 - 1);
+            const int r = j == 0 ? t : max(t + NT - SHIFT, NT);
             const int bx = r % TL::BX - 2, by = r / TL::BX - 2;
             sxy[j] = (wrapc(y0 + by, g.ny) * g.nx + wrapc(x0 + bx, g.nx)) * SB;
         }
-        // The loads of later planes are issued on every lane and in every iteration: a lane past
-        // the staged sites repeats the last site's load, and past the chunk's end the last plane
-        // it needs is read again (an L2 hit); neither value is used.  Values defined on every path need no register copies between the
-        // loop's iterations.
+        // Past the chunk's end the last plane it needs is read again (an L2 hit) and not used:
+        // loads issued on every path need no register copies between the loop's iterations.
         R sraw[NSTAGE][NB];
         R praw[Q];
         auto stage_issue = [&](int q) {
             const int zb = zoff(q) * SB;
-#pragma unroll
-            for (int j = 0; j < NSTAGE; j++)
-                Unroll<0, NB>::run([&](auto c) { sraw[j][c] = bB.template loadraw<c>(sxy[j], zb); });
+            Unroll<0, NB>::run([&](auto c) { sraw[0][c] = bB.template loadraw<c>(sxy[0], zb); });
+            if (stage2) Unroll<0, NB>::run([&](auto c) { sraw[1][c] = bB.template loadraw<c>(sxy[1], zb); });
         };
         auto stage_commit = [&](int q) {
             C *dst = bst[sslot(q)];
-#pragma unroll
-            for (int j = 0; j < NSTAGE; j++) {
-                const int r = t + j * NT;
-                if (r < NB2) {
-                    Unroll<0, NB>::run([&](auto c) { dst[c * NB2 + r] = bB.template decode<c, Q>(sraw[j][c], cd); });
-                }
+            Unroll<0, NB>::run([&](auto c) { dst[c * NB2 + t] = bB.template decode<c, Q>(sraw[0][c], cd); });
+            if (stage2 && t >= SHIFT) {
+                const int r = t + NT - SHIFT;
+                Unroll<0, NB>::run([&](auto c) { dst[c * NB2 + r] = bB.template decode<c, Q>(sraw[1][c], cd); });
             }
         };
         auto pops_issue = [&](int p) {
