@@ -385,12 +385,10 @@ int capture_graph(lbm_server *s) {
 void retire(lbm_server *s, Request &r, bool check_only) {
     long counts[2] = {0, 0};
     double umax = 0;
-    int hc = lbm_health(r.lat, counts, &umax);
-    unsigned range = 0;
-    if (hipMemcpyAsync(&range, r.lat->flag, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess)
-        hc = LBM_ERR_HIP;
-    if (hc != LBM_OK || range) {
+    // lbm_health reads and clears the 16-bit overflow flag: LBM_ERR_RANGE, before DIVERGED
+    const int hc = lbm_health(r.lat, counts, &umax);
+    const bool range = hc == LBM_ERR_RANGE;
+    if (hc != LBM_OK) {
         // A binary16 code past its largest finite value means a deviation grew 1024-fold beyond
         // the largest initial one, which in practice is a diverging run; a bfloat16 code is
         // flagged only when the value itself is no longer finite.
