@@ -515,3 +515,30 @@ def test_fp16_overflow_is_reported_as_range(kernel):
     assert g.health()[:2] == (0, 0)
     g.step(3)
     assert g.health()[:2] == (0, 0)
+
+
+@pytest.mark.parametrize("dims", [(5, 3, 3), (64, 8, 3), (65, 9, 4), (130, 17, 5)])
+@pytest.mark.parametrize("mode", ["thermal", "iso"])
+def test_split_sweep_all_terms_against_oracle(dims, mode):
+    # The split sweep with every term at once, FP32 against the oracle (<= 1e-5): references
+    # shifted off rho = 1, T = 1/3 (the K e_i terms), a body-force field and a ghost rate.  The
+    # shapes take one plane per z chunk past the warm-up (nz = 3, 4, 5), lattices narrower than
+    # the 64 x 8 tile (its lanes wrap onto the same sites and store nothing), one exact tile, and
+    # ragged tiles in x and y.
+    tau, tau_g, steps = 0.7, 0.55, 12
+    rho, u, T = wl.fourier_fields(*dims, seed=47, u_max=0.2, T0=0.3)
+    rho = 0.8 * rho
+    rho_ref, T_ref = lbm().codec_reference(rho, T)
+    _, a, _ = wl.fourier_fields(*dims, seed=48, u_max=1.0)
+    a = 3e-4 * a
+    nx, ny, nz = dims
+    g = lbm().Lattice(nx, ny, nz, tau, storage="f32", mode=mode, kernel="fused_pc", rho_ref=rho_ref, T_ref=T_ref)
+    g.set_ghost_relaxation(tau_g)
+    g.set_fields(rho, u, T)
+    g.set_body_force(a)
+    o = oracle.OracleLattice(nx, ny, nz, tau, mode=mode, tau_ghost=tau_g)
+    o.init(rho, u, T)
+    o.set_body_force(a)
+    g.step(steps)
+    o.step(steps)
+    compare(g, o, 1e-5, f"split sweep, all terms, {dims} {mode}")
