@@ -187,6 +187,13 @@ int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost);
  * collision does.  Errors: ARG (dtype, projected lattice), OOM, HIP. */
 int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device);
 
+/* A uniform body-force acceleration: accel is a host array of 3 values (x, y, z), or NULL to remove
+ * the body force; it replaces a field set by lbm_set_body_force (and that call replaces it).  The
+ * same forcing as a field holding the vector at every site, bit for bit, without the field's
+ * device memory or its 3 reads per site (the paper's channels are driven by a uniform force).
+ * Errors: ARG (non-finite value, projected lattice). */
+int lbm_set_body_force_uniform(lbm_handle h, const double *accel);
+
 /* Walls normal to z (the channels of Sec. III A and C): on = 1 places one wall half-way below
  * plane 0 and one half-way above plane nz - 1 (z = -1/2 and nz - 1/2); x and y stay periodic.
  * u_bottom, u_top: host arrays of 3 wall velocities (NULL: at rest); the z components must be 0.

@@ -504,7 +504,7 @@ int lbm_set_projection(lbm_handle h, int dims) {
         if (h->p.mode == LBM_STANDARD) return fail(LBM_ERR_ARG, "the standard comparator is not projected");
         if (h->kernel == 2 || h->kernel == 3)
             return fail(LBM_ERR_ARG, "projected lattices step with their own two-pass kernels");
-        if (h->walls || h->accel || h->tau_ghost > 0.0)
+        if (h->walls || h->accel || h->force_uniform || h->tau_ghost > 0.0)
             return fail(LBM_ERR_ARG, "projected lattices have no walls, body force or ghost rate");
     }
     HIP_TRY(h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize());
@@ -565,6 +565,8 @@ int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device
         (void)hipFree(h->accel);
         h->accel = nullptr;
     }
+    h->force_uniform = 0;
+    for (int c = 0; c < 3; c++) h->acc_u[c] = 0.0;
     if (!accel) return LBM_OK;
     if (dtype != LBM_DTYPE_F64 && dtype != LBM_DTYPE_F32) return fail(LBM_ERR_ARG, "unknown dtype %d", dtype);
     if (h->proj < 3) return fail(LBM_ERR_ARG, "projected lattices have no body force");
@@ -596,6 +598,20 @@ int lbm_set_body_force(lbm_handle h, const void *accel, int dtype, int on_device
     if (stage) (void)hipFree(stage);
     if (!rc && e != hipSuccess) rc = fail(LBM_ERR_HIP, "body force: %s", hipGetErrorString(e));
     return rc;
+}
+
+int lbm_set_body_force_uniform(lbm_handle h, const double *accel) {
+    if (!h) return fail(LBM_ERR_ARG, "null handle");
+    if (accel) {
+        for (int c = 0; c < 3; c++)
+            if (!std::isfinite(accel[c])) return fail(LBM_ERR_ARG, "body force not finite");
+        if (h->proj < 3) return fail(LBM_ERR_ARG, "projected lattices have no body force");
+    }
+    if (int rc = lbm_set_body_force(h, nullptr, 0, 0)) return rc;  // drops a field
+    if (!accel) return LBM_OK;
+    h->force_uniform = 1;
+    for (int c = 0; c < 3; c++) h->acc_u[c] = accel[c];
+    return LBM_OK;
 }
 
 int lbm_set_ghost_relaxation(lbm_handle h, double tau_ghost) {

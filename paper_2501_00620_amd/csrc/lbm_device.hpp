@@ -142,6 +142,8 @@ template <typename C> struct StepConst {
     C K;          // rho_ref * theta_ref
     C om1;        // 1 - omega
     C ghost;      // 1 - omega_g / omega: the non-hydrodynamic moments' own rate (0: single rate)
+    C au[3];      // uniform body-force acceleration (when force_u)
+    int force_u;  // 1: a uniform body force acts (no acceleration field)
     C uwb[3];     // velocity of the wall below plane 0 (walls; tangential)
     C uwt[3];     // velocity of the wall above plane nz - 1
     int iso;      // prescribed temperature (theta per site or constant)
@@ -357,6 +359,21 @@ __device__ __forceinline__ void grad_finish_thin(const GradAcc<C> &g, C F[3], C 
     for (int c = 0; c < 3; c++) S[c] = -(g.fS[c] * C(2.0 / 3.0) + g.eS[c] * C(1.0 / 6.0));
 #pragma unroll
     for (int c = 3; c < 6; c++) S[c] = -(g.fS[c] * C(1.0 / 3.0) + g.eS[c] * C(1.0 / 12.0));
+}
+
+// The body-force acceleration at site s: the field (3 planes of n values) if there is one, else
+// the uniform vector of the step constants.
+template <typename C>
+__device__ __forceinline__ void site_accel(const StepConst<C> &k, const C *accel, size_t n, size_t s, C a[3]) {
+    if (accel) {
+        a[0] = accel[s];
+        a[1] = accel[n + s];
+        a[2] = accel[2 * n + s];
+    } else {
+        a[0] = k.au[0];
+        a[1] = k.au[1];
+        a[2] = k.au[2];
+    }
 }
 
 // A body-force acceleration a in the forcing moments, in the manner of a Guo forcing:

@@ -321,7 +321,8 @@ __device__ __forceinline__ void source_site_staged(const Buf<S> &bF, const typen
 // (one LDS slot of each kind, about a third of the LDS, so that several work-groups share a CU).
 // amax collects |16-bit codes| stored.  NST_: populations of the tile's own sites carried in
 // LDS from the source evaluation to the collision (staged kernels only).  FORCE: a body-force
-// acceleration field `accel` (3 planes of n) enters the forcing moments before the collision.
+// acceleration (the field `accel`, 3 planes of n, or the uniform one of k) enters the forcing
+// moments before the collision.
 template <int S, bool GATHERED, bool HASK, bool THIN1 = false, typename TL = typename TileFor<S>::type, int NST_ = 0,
           bool FORCE = false>
 __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restrict__ F,
@@ -586,7 +587,8 @@ __device__ __forceinline__ void sweep_tile(const typename Storage<S>::T *__restr
         const PopMoments<C> m = pop_moments(d, k.rho_ref);
         if constexpr (FORCE) {
             const int s = zc + ixy;
-            const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
+            C a[3];
+            site_accel(k, accel, g.n, s, a);
             add_body_force(m, a, Fv, Sv);
         }
         collide(d, cur.beta, m, Fv, Sv, cur.theta, k);
@@ -687,7 +689,8 @@ __device__ __forceinline__ void report_range(const RangeMax &rm, const Codec &cd
 #endif
 
 // Occupancy: the LDS (159 KB of 160 KB with the kept populations) admits one 512-thread
-// work-group per CU, i.e. two waves per SIMD.  FORCE: with a body-force field (accel).
+// work-group per CU, i.e. two waves per SIMD.  FORCE: with a body force (the field accel, or
+// the uniform acceleration of the step constants).
 template <int S, bool GATHERED, bool HASK, bool THIN1, bool FORCE>
 __global__ void __launch_bounds__(TileFor<S>::type::NT) __attribute__((amdgpu_waves_per_eu(FUSED_WAVES_PER_EU)))
 k_fused(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,

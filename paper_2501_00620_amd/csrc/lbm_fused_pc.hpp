@@ -414,7 +414,8 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                     cur.theta = site_T(Tf, Tconst, s);
                     const PopMoments<C> m = pop_moments(d, k.rho_ref);
                     if constexpr (FORCE) {
-                        const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
+                        C a[3];
+                        site_accel(k, accel, g.n, s, a);
                         add_body_force(m, a, Fv, Sv);
                     }
                     C g0[MRT ? 9 : 1];

@@ -33,6 +33,8 @@ struct lbm_lattice {
     int slots_pc = 256;         // the same for the producer/consumer sweep
     double tau_ghost = -1.0;    // relaxation time of Table I rows 11-19 (<= 0: the single rate)
     void *accel = nullptr;      // body-force acceleration, 3 planes of the compute type, or null
+    int force_uniform = 0;      // 1: a uniform body-force acceleration acc_u (no field)
+    double acc_u[3] = {0, 0, 0};
     int walls = 0;              // 1: walls normal to z bound the lattice (lbm_set_walls)
     double uw[6] = {0, 0, 0, 0, 0, 0};  // velocities of the bottom and top walls
     int proj = 3;               // 3: D3Q19; 2, 1: the projected lattice of lbm_set_projection
@@ -69,7 +71,9 @@ template <typename C> inline StepConst<C> step_const(const lbm_lattice *h) {
     for (int c = 0; c < 3; c++) {
         k.uwb[c] = (C)h->uw[c];
         k.uwt[c] = (C)h->uw[3 + c];
+        k.au[c] = (C)h->acc_u[c];
     }
+    k.force_u = h->force_uniform && !h->accel;
     k.iso = h->p.mode == LBM_ISO;
     return k;
 }

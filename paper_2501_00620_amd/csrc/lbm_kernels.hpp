@@ -172,8 +172,9 @@ k_collide(const typename Storage<S>::T *__restrict__ F, const typename Storage<S
     load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, f, bbar, m, zw);
     C Fv[3], Sv[6];
     gradient_from_src<WALLS>(src, g.n, nb, k.K, Fv, Sv, zw, g.nx * g.ny);
-    if (accel) {  // body force (uniform branch: one field for the whole lattice)
-        const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
+    if (accel || k.force_u) {  // body force (a branch uniform over the launch)
+        C a[3];
+        site_accel(k, accel, g.n, s, a);
         add_body_force(m, a, Fv, Sv);
     }
     C g0[MRT ? 9 : 1];
@@ -215,8 +216,9 @@ k_readout(const typename Storage<S>::T *__restrict__ F, const typename Storage<S
     load_site<S, GATHERED>(F, B, g.n, nb, s, cd, k.rho_ref, f, bbar, m, zw);
     C Fv[3], Sv[6];
     gradient_from_src<true>(src, g.n, nb, k.K, Fv, Sv, zw, g.nx * g.ny);
-    if (accel) {
-        const C a[3] = {accel[s], accel[(size_t)g.n + s], accel[2 * (size_t)g.n + s]};
+    if (accel || k.force_u) {
+        C a[3];
+        site_accel(k, accel, g.n, s, a);
         add_body_force(m, a, Fv, Sv);
     }
     C uc[3], Tc;
@@ -309,8 +311,10 @@ k_std(const typename Storage<S>::T *__restrict__ F, typename Storage<S>::T *__re
     const PopMoments<C> m = pop_moments(d, k.rho_ref);
     const C inv = recip(m.rho);
     const C th = site_T(Tf, Tconst, s) + k.theta_ref;
-    if (accel) {  // uniform branch: one field for the whole lattice
-        const C Fv[3] = {m.rho * accel[s], m.rho * accel[(size_t)g.n + s], m.rho * accel[2 * (size_t)g.n + s]};
+    if (accel || k.force_u) {  // a branch uniform over the launch
+        C a[3];
+        site_accel(k, accel, g.n, s, a);
+        const C Fv[3] = {m.rho * a[0], m.rho * a[1], m.rho * a[2]};
         const C u[3] = {fma(C(0.5), Fv[0], m.jx) * inv, fma(C(0.5), Fv[1], m.jy) * inv,
                         fma(C(0.5), Fv[2], m.jz) * inv};
         const C Sv[6] = {C(2) * u[0] * Fv[0], C(2) * u[1] * Fv[1], C(2) * u[2] * Fv[2],
@@ -355,9 +359,11 @@ k_readout_std(const typename Storage<S>::T *__restrict__ F, const typename Stora
     Unroll<0, Q>::run([&](auto I) { d[I] = Storage<S>::load(F, (size_t)I * g.n + s, I, cd); });
     const PopMoments<C> m = pop_moments(d, k.rho_ref);
     C j[3] = {m.jx, m.jy, m.jz};
-    if (accel) {
+    if (accel || k.force_u) {
+        C a[3];
+        site_accel(k, accel, g.n, s, a);
 #pragma unroll
-        for (int c = 0; c < 3; c++) j[c] = fma(C(0.5) * m.rho, accel[(size_t)c * g.n + s], j[c]);
+        for (int c = 0; c < 3; c++) j[c] = fma(C(0.5) * m.rho, a[c], j[c]);
     }
     if (rho) rho[s] = (OUT)((double)k.rho_ref + (double)m.drho);
     if (u) {

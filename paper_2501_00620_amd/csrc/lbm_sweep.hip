@@ -28,7 +28,7 @@ int launch_fused(const typename Storage<S>::T *F, const typename Storage<S>::T *
     // one z plane: the instantiation with the in-plane gather and gradient (the serving kernel
     // sweeps such lattices with the same arithmetic)
     auto go = [&](auto G, auto H, auto T1) {
-        if (accel)
+        if (accel || k.force_u)
             hipLaunchKernelGGL((k_fused<S, decltype(G)::value, decltype(H)::value, decltype(T1)::value, true>), grid,
                                block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg, accel);
         else
@@ -65,7 +65,7 @@ int launch_fused_pc(const typename Storage<S>::T *F, const typename Storage<S>::
     using tt = std::true_type;
     using ff = std::false_type;
     auto with_mrt = [&](auto H, auto FO) { k.ghost != 0 ? go(H, FO, tt{}) : go(H, FO, ff{}); };
-    auto with_force = [&](auto H) { accel ? with_mrt(H, tt{}) : with_mrt(H, ff{}); };
+    auto with_force = [&](auto H) { accel || k.force_u ? with_mrt(H, tt{}) : with_mrt(H, ff{}); };
     k.K != 0 ? with_force(tt{}) : with_force(ff{});
     return 0;
 }

@@ -54,6 +54,7 @@ SIGNATURES = {
     "lbm_set_ghost_relaxation": ([C.c_void_p, C.c_double], C.c_int),
     "lbm_set_body_force": ([C.c_void_p, C.c_void_p, C.c_int, C.c_int], C.c_int),
     "lbm_set_walls": ([C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+    "lbm_set_body_force_uniform": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
     "lbm_set_projection": ([C.c_void_p, C.c_int], C.c_int),
     "lbm_get_projection": ([C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "lbm_sync": ([C.c_void_p], C.c_int),
@@ -169,13 +170,17 @@ class Lattice:
     def set_kernel(self, kernel):
         _check(_lib.lbm_set_kernel(self._h, KERNEL[kernel] if isinstance(kernel, str) else int(kernel)))
 
-    def set_body_force(self, accel):
-        """Body-force acceleration: an array (3, nz, ny, nx), a 3-vector (uniform), or None to
-        remove it.  Both the fused and the two-pass step take it."""
+    def set_body_force(self, accel, field=False):
+        """Body-force acceleration: an array (3, nz, ny, nx), a 3-vector (uniform; with
+        field=True it is broadcast to a field instead), or None to remove it.  Both the fused and
+        the two-pass step take it."""
         if accel is None:
             _check(_lib.lbm_set_body_force(self._h, None, 0, 0))
             return
         a = np.asarray(accel, dtype=np.float64)
+        if a.size == 3 and not field:
+            _check(_lib.lbm_set_body_force_uniform(self._h, (C.c_double * 3)(*a.reshape(3))))
+            return
         shape = (3, self.nz, self.ny, self.nx)
         a = np.ascontiguousarray(np.broadcast_to(a.reshape(3, 1, 1, 1) if a.size == 3 else a, shape))
         _check(_lib.lbm_set_body_force(self._h, a.ctypes.data_as(C.c_void_p), 0, 0))

@@ -138,3 +138,57 @@ def test_body_force_argument_errors():
     g = L.Lattice(8, 8, 8, 0.7, storage="f32", kernel="fused")
     g.set_body_force([1e-4, 0, 0])
     g.set_kernel("fused")
+
+
+@pytest.mark.parametrize("kernel", ["fused", "fused_pc", "two_pass"])
+@pytest.mark.parametrize("mode", ["thermal", "iso", "standard"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+def test_uniform_force_equals_the_same_field(kernel, mode, storage):
+    # lbm_set_body_force_uniform: the forcing of a field holding the vector at every site, bit for
+    # bit, in every kernel that takes a force (and the readout of the moments)
+    if kernel == "fused_pc" and (storage == "f64" or mode == "standard"):
+        pytest.skip("the split sweep has no double-precision instantiation; STANDARD steps its own kernel")
+    if kernel == "fused" and mode == "standard":
+        pytest.skip("STANDARD steps its own kernel")
+    dims = (19, 10, 6)
+    fields = wl.fourier_fields(*dims, seed=51, u_max=0.15)
+    a = [2e-4, -1e-4, 3e-4]
+    out = []
+    for field in (False, True):
+        g = lbm().Lattice(*dims, 0.7, storage=storage, mode=mode, kernel=kernel)
+        g.set_fields(*fields)
+        g.set_body_force(a, field=field)
+        g.step(7)
+        F, b = g.get_state()
+        r, u, T = g.moments()
+        out.append([q.cpu().numpy() for q in (F, b, r, u, T)])
+    for x, y in zip(*out):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_uniform_force_replaces_and_is_replaced():
+    L = lbm()
+    dims = (12, 10, 8)
+    fields = wl.fourier_fields(*dims, seed=52, u_max=0.1)
+
+    def run(setup):
+        g = L.Lattice(*dims, 0.7, storage="f32")
+        g.set_fields(*fields)
+        setup(g)
+        g.step(5)
+        return g.get_state()[0].cpu().numpy()
+
+    plain = run(lambda g: None)
+    # set, then removed: the force-free step
+    np.testing.assert_array_equal(run(lambda g: (g.set_body_force([1e-4, 0, 0]), g.set_body_force(None))), plain)
+    # a field replaces the uniform force, and the uniform force a field
+    field = run(lambda g: g.set_body_force([0, 2e-4, 0], field=True))
+    np.testing.assert_array_equal(run(lambda g: (g.set_body_force([1e-4, 0, 0]), g.set_body_force([0, 2e-4, 0], field=True))), field)
+    np.testing.assert_array_equal(run(lambda g: (g.set_body_force(np.full((3,) + dims[::-1], 1e-3)), g.set_body_force([0, 2e-4, 0]))), field)
+    p = L.Lattice(8, 8, 1, 0.7, storage="f32")
+    p.set_projection(2)
+    with pytest.raises(L.LBMError):
+        p.set_body_force([1e-4, 0, 0])
+    q = L.Lattice(8, 8, 8, 0.7, storage="f32")
+    with pytest.raises(L.LBMError):
+        q.set_body_force([float("nan"), 0, 0])
