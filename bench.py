@@ -30,8 +30,9 @@ Also reported on the same JSON line:
                 viscosity in a moving frame, bump vs standard scheme), the MRT step's
                 throughput beside the single-rate two-pass step, the body force (fused and two-pass
                 throughput; Kolmogorov-flow amplitude against A / (T tau k^2)), and the walls
-                (two-pass channel throughput; the gravity Couette flow of Sec. III C in two
-                frames, bump vs standard, against its closed form);
+                (channel throughput in the split fused sweep and two-pass, beside the periodic
+                sweep; the gravity Couette flow of Sec. III C in two frames, bump vs standard,
+                against its closed form);
   cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample (a 48^3 Taylor-Green
                 vortex for ~10 s) with OpenMP on all allowed threads, and again on one core;
                 the CPU model.
@@ -414,8 +415,10 @@ def body_force(n=256, tau=0.55, mach=0.5, steps=100, N=64, T0=0.2, tau_k=0.6, A=
 
 
 def walls(n=256, tau=0.55, mach=0.5, steps=100, nz=32, T0=1.0 / 6.0, tau_c=0.8, ratio=2.0, U=0.02):
-    """Walls: the two-pass step of a 256^3 channel (walls at rest normal to z, a driving
-    acceleration along y) on the Taylor-Green input; and the gravity Couette flow of the paper's
+    """Walls: a 256^3 channel (walls at rest normal to z, a driving acceleration along y) on the
+    Taylor-Green input, stepped by the split fused sweep (interior planes; the wall planes with the
+    wall kernel) and by the two-pass step, beside the periodic split sweep with the same force;
+    and the gravity Couette flow of the paper's
     Galilean test on the GPU, walls moving at (0, 2U) and at (-U, U) under a_z = -g with
     g = ratio T / nz (density ratio e^ratio), in the bump scheme (prescribed T) and the standard
     comparator, against the closed form u_y = (u_t - u_b)(1 - e^(g z'/T)) / (1 - e^(g H/T)) + u_b."""
@@ -426,14 +429,18 @@ def walls(n=256, tau=0.55, mach=0.5, steps=100, nz=32, T0=1.0 / 6.0, tau_c=0.8, 
     out = {"workload": f"channel {n}^3 FP32 (Taylor-Green input, walls normal to z, uniform acceleration); "
                        f"gravity Couette {nz} x 1 x 1, T {T0:.4g}, tau {tau_c}, density ratio e^{ratio:g}, "
                        f"U {U}, {40 * nz * nz} steps"}
-    lat = lbm.Lattice(n, n, n, tau, storage="f32")
-    lat.set_fields(rho, u, T)
-    lat.set_walls()
-    lat.set_body_force([0.0, 1e-5, 0.0])
-    secs = timed_steps(lat, steps, 5)
-    out["two_pass_mlups"] = n ** 3 * steps / secs / 1e6
-    del lat
-    torch.cuda.empty_cache()
+    for kernel, with_walls, key in (("auto", True, "fused_mlups"), ("two_pass", True, "two_pass_mlups"),
+                                    ("auto", False, "periodic_fused_mlups")):
+        lat = lbm.Lattice(n, n, n, tau, storage="f32", kernel=kernel)
+        lat.set_fields(rho, u, T)
+        if with_walls:
+            lat.set_walls()
+        lat.set_body_force([0.0, 1e-5, 0.0])
+        secs = timed_steps(lat, steps, 5)
+        out[key] = n ** 3 * steps / secs / 1e6
+        del lat
+        torch.cuda.empty_cache()
+    out["fused_over_periodic"] = out["fused_mlups"] / out["periodic_fused_mlups"]
     g = ratio * T0 / nz
     zp = np.arange(nz) + 0.5
     for mode in ("iso", "standard"):
@@ -452,7 +459,8 @@ def walls(n=256, tau=0.55, mach=0.5, steps=100, nz=32, T0=1.0 / 6.0, tau_c=0.8, 
         key = "bump" if mode == "iso" else "standard"
         out[key] = {"max_err_over_2U": float(max(np.abs(p - e).max() for p, e in prof) / (2 * U)),
                     "frame_difference_over_U": float(np.abs(prof[0][0] - U - prof[1][0]).max() / U)}
-    print(f"[bench] walls: two-pass channel {out['two_pass_mlups']:.0f} MLUPS; gravity Couette frame difference "
+    print(f"[bench] walls: channel {out['fused_mlups']:.0f} MLUPS fused ({out['fused_over_periodic']:.3f} of periodic "
+          f"{out['periodic_fused_mlups']:.0f}), two-pass {out['two_pass_mlups']:.0f}; gravity Couette frame difference "
           f"bump {out['bump']['frame_difference_over_U']:.3f} U, standard {out['standard']['frame_difference_over_U']:.3f} U",
           file=sys.stderr, flush=True)
     return out

@@ -160,11 +160,13 @@ int lbm_health(lbm_handle h, long counts[2], double *max_u);
  * (predictor sources) and consumer waves (gradient, collision, stream) of one work-group, for
  * float and 16-bit storage on lattices with nz >= 3.  All give the same step up to the order of
  * the gradient sums.  Auto takes the split sweep where it applies (from the second step after
- * the state was set; the first gathers bbar in the single-role sweep), a ghost rate and a body
- * force included; else the single-role fused sweep, for a periodic single-rate lattice (with or
- * without a body force) whose buffers fit their 32-bit offsets; else the two-pass step (walls).
- * Errors: ARG (bad choice; a fused sweep on a projected lattice, on walls or beyond its offsets;
- * the single-role sweep with a ghost rate; the split sweep in double precision or below 3
+ * the state was set; the first gathers bbar in the single-role sweep, or two-pass with walls), a
+ * ghost rate, a body force and walls included; else the single-role fused sweep, for a periodic
+ * single-rate lattice (with or without a body force) whose buffers fit their 32-bit offsets; else
+ * the two-pass step.  With walls the split sweep steps the interior planes 1 .. nz-2, and the two
+ * wall planes step with the two-pass wall kernel in the same lbm_step.
+ * Errors: ARG (bad choice; a fused sweep on a projected lattice or beyond its offsets; the
+ * single-role sweep with walls or a ghost rate; the split sweep in double precision or below 3
  * planes). */
 int lbm_set_kernel(lbm_handle h, int kernel);
 
@@ -201,8 +203,10 @@ int lbm_set_body_force_uniform(lbm_handle h, const double *accel);
  * bounce-back) carrying the moving-wall momentum of Ladd, 6 w_i rho e_i.u_w, and the site's own
  * variance.  Beyond a wall the gradient sources of Eqs. 59 and 61 take the wall-adjacent
  * plane's rho b (mirrored) and the second-order extrapolation of rho b u*.  on = 0 restores the
- * periodic z direction.  Applies to every mode; a lattice with walls steps with the two-pass
- * kernel.  Errors: ARG (nz < 3, a normal or non-finite wall velocity, a fused kernel forced). */
+ * periodic z direction.  Applies to every mode.  A float or 16-bit lattice with walls steps its
+ * interior planes with the split fused sweep and its two wall planes with the two-pass wall
+ * kernel (lbm_set_kernel); double precision steps two-pass.  Errors: ARG (nz < 3, a normal or
+ * non-finite wall velocity, the single-role fused kernel forced by lbm_set_kernel(h, 2)). */
 int lbm_set_walls(lbm_handle h, int on, const double *u_bottom, const double *u_top);
 
 /* Projected lattice (the lower-dimensional bump lattices that Sec. II B illustrates with D1Q3):
@@ -247,8 +251,8 @@ const char *lbm_last_error(void);
 long lbm_steps_done(lbm_handle h);
 
 /* Device bytes a lattice with these parameters occupies (what lbm_create allocates).  A lattice
- * that steps two-pass (lbm_set_kernel(h, 1), walls, or a ghost rate in double precision or below
- * 3 planes) allocates 9 more planes of the compute type at its first step. */
+ * that steps two-pass (lbm_set_kernel(h, 1), or a ghost rate in double precision or below 3
+ * planes) or has walls allocates 9 more planes of the compute type at its first such step. */
 size_t lbm_lattice_bytes(const lbm_params *p);
 
 /* ---------------------------------------------------------------------------------------------

@@ -213,36 +213,62 @@ int ensure_src(lbm_lattice *h) {
     return LBM_OK;
 }
 
-template <int S> int step_two_pass(lbm_lattice *h) {
+// The two-pass step's launches on the current state: the predictor over planes [z0, z1) into
+// the source planes, and the collision over planes [c0, c1) (both ends plane indices; the wall
+// kernel on planes 0 and nz-1 when the lattice has walls).
+template <int S> struct TwoPass {
     using T = typename Storage<S>::T;
     using C = typename Storage<S>::C;
+    lbm_lattice *h;
+    Geo g;
+    StepConst<C> k;
+    const T *F, *B;
+    T *Fo, *Bo;
+    C *src;
+    explicit TwoPass(lbm_lattice *hh)
+        : h(hh), g(geo(hh)), k(step_const<C>(hh)), F((const T *)hh->F[hh->cur]), B((const T *)hh->B[hh->cur]),
+          Fo((T *)hh->F[1 - hh->cur]), Bo((T *)hh->B[1 - hh->cur]), src((C *)hh->src) {}
+    int nxy() const { return h->p.nx * h->p.ny; }
+    template <bool G> void predict(int z0, int z1) const {
+        const int s0 = z0 * nxy(), count = (z1 - z0) * nxy();
+        hipLaunchKernelGGL((k_predict<S, G>), dim3(blocks_for(count)), dim3(BLOCK), 0, h->stream, F, B, src,
+                           (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, s0, count);
+    }
+    template <bool G, bool M, bool W> void collide(int z0, int z1) const {
+        const int s0 = z0 * nxy(), count = (z1 - z0) * nxy();
+        hipLaunchKernelGGL((k_collide<S, G, M, W>), dim3(blocks_for(count)), dim3(BLOCK), 0, h->stream, F, B, src, Fo,
+                           Bo, (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->flag, (const C *)h->accel, s0,
+                           count);
+    }
+    // The wall planes 0 and nz-1, stepped with the wall kernel, and the sources of the planes
+    // next to them (which the split sweep's gradients of planes 1 and nz-2 read too).
+    template <bool M> void wall_planes() const {
+        const int nz = h->p.nz;
+        if (nz <= 6) {
+            predict<false>(0, nz);
+        } else {
+            predict<false>(0, 3);
+            predict<false>(nz - 3, nz);
+        }
+        collide<false, M, true>(0, 1);
+        collide<false, M, true>(nz - 1, nz);
+    }
+};
+
+template <int S> int step_two_pass(lbm_lattice *h) {
     if (int rc = ensure_src(h)) return rc;
-    const Geo g = geo(h);
-    const StepConst<C> k = step_const<C>(h);
-    const T *F = (const T *)h->F[h->cur];
-    const T *B = (const T *)h->B[h->cur];
-    T *Fo = (T *)h->F[1 - h->cur];
-    T *Bo = (T *)h->B[1 - h->cur];
-    C *src = (C *)h->src;
-    const C *Tf = (const C *)h->Tf;
-    const C Tc = (C)h->Tconst;
-    const dim3 grid(blocks_for(h->n)), block(BLOCK);
-    auto collide = [&](auto GI, auto MI, auto WI, int s0, int count) {
-        constexpr bool G = decltype(GI)::value, M = decltype(MI)::value, W = decltype(WI)::value;
-        hipLaunchKernelGGL((k_collide<S, G, M, W>), dim3(blocks_for(count)), block, 0, h->stream, F, B, src, Fo, Bo,
-                           Tf, Tc, g, k, h->codec, h->flag, (const C *)h->accel, s0, count);
-    };
+    const TwoPass<S> tp(h);
+    const int nz = h->p.nz;
     auto launch = [&](auto GI, auto MI) {
-        hipLaunchKernelGGL((k_predict<S, decltype(GI)::value>), grid, block, 0, h->stream, F, B, src, Tf, Tc, g, k,
-                           h->codec, 0, h->n);
+        constexpr bool G = decltype(GI)::value, M = decltype(MI)::value;
+        tp.template predict<G>(0, nz);
         if (!h->walls) {
-            collide(GI, MI, std::false_type{}, 0, h->n);
+            tp.template collide<G, M, false>(0, nz);
         } else {
             // interior planes with the periodic kernel; the two wall planes with the wall kernel
-            const int nxy = h->p.nx * h->p.ny;
-            collide(GI, MI, std::false_type{}, nxy, (h->p.nz - 2) * nxy);
-            collide(GI, MI, std::true_type{}, 0, nxy);
-            collide(GI, MI, std::true_type{}, (h->p.nz - 1) * nxy, nxy);
+            tp.template collide<G, M, false>(1, nz - 1);
+            tp.template collide<G, M, true>(0, 1);
+            tp.template collide<G, M, true>(nz - 1, nz);
         }
     };
     auto with_mrt = [&](auto GI) {
@@ -258,7 +284,8 @@ template <int S> int step_two_pass(lbm_lattice *h) {
 
 // The producer/consumer sweep steps float and 16-bit lattices that march in z, once bbar is held
 // scattered (the first step after the state was set gathers it from global memory in the
-// single-role sweep); lbm_set_kernel(2) keeps the single-role sweep throughout.
+// single-role sweep, or two-pass with walls); lbm_set_kernel(2) keeps the single-role sweep
+// throughout.
 bool use_fused_pc(const lbm_lattice *h) {
     return (h->kernel == 0 || h->kernel == 3) && !h->gathered && fused_pc_supported(geo(h), h->p.storage);
 }
@@ -271,9 +298,17 @@ template <int S> int step_fused(lbm_lattice *h) {
     int rc = 0;
     if constexpr (S != 0) {
         if (use_fused_pc(h)) {
+            if (h->walls) {
+                // the wall planes and their neighbours' sources first (two-pass kernels), then the
+                // interior planes; each writes population slots the other does not
+                if ((rc = ensure_src(h))) return rc;
+                const TwoPass<S> tp(h);
+                if (h->tau_ghost > 0.0) tp.template wall_planes<true>(); else tp.template wall_planes<false>();
+                if ((rc = check_launch())) return rc;
+            }
             rc = launch_fused_pc<S>((const T *)h->F[h->cur], (const T *)h->B[h->cur], (T *)h->F[1 - h->cur],
                                     (T *)h->B[1 - h->cur], (const C *)h->Tf, (C)h->Tconst, g, k, h->codec, h->flag,
-                                    h->slots_pc, h->stream, (const C *)h->accel);
+                                    h->slots_pc, h->stream, (const C *)h->accel, (const C *)h->src);
             if (rc) return fail(LBM_ERR_HIP, "fused launch failed");
             rc = check_launch();
             if (rc) return rc;
@@ -364,8 +399,8 @@ template <int S> int step_std(lbm_lattice *h) {
 }
 
 // Whether the next step is a fused one: the producer/consumer sweep when it takes the lattice
-// (a ghost rate included), else the single-role sweep, which relaxes with a single rate; walls
-// step two-pass.
+// (a ghost rate and walls included), else the single-role sweep, which relaxes with a single rate
+// on a periodic lattice.
 bool use_fused(const lbm_lattice *h) {
     if (h->kernel == 1) return false;
     if (use_fused_pc(h)) return true;
@@ -462,7 +497,7 @@ int lbm_set_kernel(lbm_handle h, int kernel) {
         return fail(LBM_ERR_ARG, "fused sweep does not support this lattice shape");
     if (kernel == 2 && h->tau_ghost > 0.0)
         return fail(LBM_ERR_ARG, "the single-role fused sweep relaxes with a single rate (a ghost rate is set)");
-    if (fused && h->walls) return fail(LBM_ERR_ARG, "the fused sweep is periodic (walls are set)");
+    if (kernel == 2 && h->walls) return fail(LBM_ERR_ARG, "the single-role fused sweep is periodic (walls are set)");
     if (kernel == 3 && !fused_pc_supported(geo(h), h->p.storage))
         return fail(LBM_ERR_ARG, "the producer/consumer sweep takes float or 16-bit storage and nz >= 3");
     h->kernel = kernel;
@@ -478,8 +513,8 @@ int lbm_set_walls(lbm_handle h, int on, const double *u_bottom, const double *u_
     }
     if (h->p.nz < 3) return fail(LBM_ERR_ARG, "walls need nz >= 3 (got %d)", h->p.nz);
     if (h->proj < 3) return fail(LBM_ERR_ARG, "projected lattices have no walls");
-    if (h->kernel == 2 || h->kernel == 3)
-        return fail(LBM_ERR_ARG, "the fused sweep is periodic (lbm_set_kernel chose it)");
+    if (h->kernel == 2)
+        return fail(LBM_ERR_ARG, "the single-role fused sweep is periodic (lbm_set_kernel chose it)");
     double uw[6] = {0, 0, 0, 0, 0, 0};
     for (int c = 0; c < 3; c++) {
         if (u_bottom) uw[c] = u_bottom[c];

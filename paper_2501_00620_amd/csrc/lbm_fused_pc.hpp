@@ -17,6 +17,12 @@
 // values (108-114 VGPRs per lane, no spills), so every SIMD holds four waves (two of each kind)
 // to cover each other's LDS and memory waits.
 //
+// Walls (half-way bounce-back at z = -1/2 and nz - 1/2, Sec. III A and C): the sweep updates the
+// interior planes 1 .. nz-2 only, whose gather, gradient and push cross no wall.  The sources of
+// the two wall-adjacent planes, which the gradients of planes 1 and nz-2 take, come from the
+// source planes the two-pass predictor wrote for the wall kernel (the same sources, gathered with
+// the bounce-back rule), read through descriptors bounded to one plane; the wall kernel steps
+// planes 0 and nz-1 itself.
 // LDS: four bbar* staging planes (tile plus two rings), two source planes (tile plus one ring),
 // and three hand-off planes of gathered bbar: 162,720 B of the 163,840 B a CU has.
 // The consumers read the populations of the plane they collide a second time from global memory
@@ -174,15 +180,29 @@ constexpr size_t pc_lds_bytes() {
 }
 static_assert(pc_lds_bytes() <= 163840, "producer/consumer sweep exceeds the LDS of a CU");
 
+// One plane of a source array (NSRC planes of n values, as the two-pass predictor writes them):
+// field c of lattice plane z, as a buffer descriptor whose range is that plane alone, so that no
+// offset can read outside it (a load past the range returns 0).
+template <typename C>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t src_plane_rsrc(const C *src, int c, int z, int n, int nxy) {
+    const unsigned long long a = (unsigned long long)(src + (size_t)c * n + (size_t)z * nxy);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+    void *ptr = (void *)(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(ptr, (short)0,
+                                             (int)__builtin_amdgcn_readfirstlane(nxy * (int)sizeof(C)), 0x00020000);
+}
+
 // MRT: the non-hydrodynamic moments relax at their own rate (ghost_relax, which carries the 9
-// ghost moments of the pre-collision populations across the collision).
-template <int S, bool HASK, bool FORCE, bool MRT>
+// ghost moments of the pre-collision populations across the collision).  WALLS: the interior
+// planes of a lattice with walls, the sources of planes 0 and nz-1 read from wsrc.
+template <int S, bool HASK, bool FORCE, bool MRT, bool WALLS>
 __global__ void __launch_bounds__(PC_THREADS)
 k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<S>::T *__restrict__ B,
            typename Storage<S>::T *__restrict__ Fo, typename Storage<S>::T *__restrict__ Bo,
            const typename Storage<S>::C *__restrict__ Tf, typename Storage<S>::C Tconst, Geo g,
            StepConst<typename Storage<S>::C> k, Codec cd, unsigned *__restrict__ flag, FusedGeo fg,
-           const typename Storage<S>::C *__restrict__ accel) {
+           const typename Storage<S>::C *__restrict__ accel, const typename Storage<S>::C *__restrict__ wsrc) {
     static_assert(S != 0, "double precision keeps the single-role sweep");
     using C = typename Storage<S>::C;
     using T = typename Storage<S>::T;
@@ -211,8 +231,9 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
     bFo.init(Fo, Q, g.n);
     bBo.init(Bo, NB, g.n);
 
-    const int z0 = chunk * fg.zchunk;
-    const int z1 = min(z0 + fg.zchunk, g.nz);
+    // the chunk's planes [z0, z1): of 0 .. nz-1, or of the interior planes 1 .. nz-2 with walls
+    const int z0 = (WALLS ? 1 : 0) + chunk * fg.zchunk;
+    const int z1 = min(z0 + fg.zchunk, WALLS ? g.nz - 1 : g.nz);
     const int nxy = g.nx * g.ny;
     const bool producer = threadIdx.x < NT;
     const int t = threadIdx.x & (NT - 1);
@@ -309,8 +330,26 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
             // staged plane p+2 for the next iteration (its slot last served plane p-2)
             stage_commit(p + 2);
             stage_issue(min(p + 3, z1 + 1));
-            const C *bs[3] = {bst[sslot(p - 1)], bst[sslot(p)], bst[sslot(p + 1)]};
             C *plane = lsrc[cslot(p)];
+            if constexpr (WALLS) {
+                static_assert(sizeof(C) == 4, "the wall planes' sources are read as 32-bit values");
+                if (p == 0 || p == g.nz - 1) {  // a wall-adjacent plane (wave-uniform): no gather here
+#pragma unroll
+                    for (int c = 0; c < NSRC; c++) {
+                        const __amdgpu_buffer_rsrc_t rs = src_plane_rsrc(wsrc, c, p, g.n, nxy);
+                        plane[c * NS + iidx] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, ixy * 4, 0, 0));
+#pragma unroll
+                        for (int j = 0; j < NRING; j++)
+                            if (t + j * NT < TL::NH)
+                                plane[c * NS + rlidx[j]] =
+                                    __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, rxy[j] * 4, 0, 0));
+                    }
+                    pops_issue(min(p + 1, z1));
+                    __syncthreads();
+                    continue;
+                }
+            }
+            const C *bs[3] = {bst[sslot(p - 1)], bst[sslot(p)], bst[sslot(p + 1)]};
             const int zo = zoff(p);
             SiteState<C> keep;
             source_site_pc<S, TL, true>(bF, praw, Tf, Tconst, k, cd, zo + ixy, ibidx, bs, plane, iidx, keep);
@@ -452,9 +491,10 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
 }
 
 // Shapes the producer/consumer sweep takes: float and 16-bit storage, more than two z planes
-// (it marches), buffers within the fused sweep's 32-bit offsets.
+// (it marches; with walls at least one interior plane), buffers within the fused sweep's 32-bit
+// offsets.
 inline bool fused_pc_supported(const Geo &g, int storage) {
-    return storage != 0 && g.nz >= 3 && !g.walls && fused_supported(g, storage);
+    return storage != 0 && g.nz >= 3 && fused_supported(g, storage);
 }
 
 }  // namespace lbm

@@ -48,19 +48,28 @@ int launch_fused(const typename Storage<S>::T *F, const typename Storage<S>::T *
     return 0;
 }
 
-// Resident work-groups per CU of the producer/consumer sweep: one (its LDS).
+// Resident work-groups per CU of the producer/consumer sweep: one (its LDS).  With walls the
+// chunks cover the interior planes 1 .. nz-2, and wsrc holds the source planes of planes 0 and
+// nz-1 (NSRC planes of n values).
 template <int S>
 int launch_fused_pc(const typename Storage<S>::T *F, const typename Storage<S>::T *B, typename Storage<S>::T *Fo,
                     typename Storage<S>::T *Bo, const typename Storage<S>::C *Tf, typename Storage<S>::C Tconst,
                     const Geo &g, const StepConst<typename Storage<S>::C> &k, const Codec &cd, unsigned *flag, int slots,
-                    hipStream_t stream, const typename Storage<S>::C *accel) {
-    const FusedGeo fg = fused_geometry_t<PcTile>(g, slots);
+                    hipStream_t stream, const typename Storage<S>::C *accel, const typename Storage<S>::C *wsrc) {
+    if (g.walls && (g.nz < 3 || !wsrc)) return -1;
+    Geo gi = g;
+    if (g.walls) gi.nz = g.nz - 2;
+    const FusedGeo fg = fused_geometry_t<PcTile>(gi, slots);
     const long long blocks = (long long)fg.tiles_x * fg.tiles_y * fg.nchunks;
     if (blocks > 2147483647LL) return -1;
     const dim3 grid((unsigned)blocks), block(PC_THREADS);
     auto go = [&](auto H, auto FO, auto M) {
-        hipLaunchKernelGGL((k_fused_pc<S, decltype(H)::value, decltype(FO)::value, decltype(M)::value>), grid, block, 0,
-                           stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg, accel);
+        if (g.walls)
+            hipLaunchKernelGGL((k_fused_pc<S, decltype(H)::value, decltype(FO)::value, decltype(M)::value, true>), grid,
+                               block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg, accel, wsrc);
+        else
+            hipLaunchKernelGGL((k_fused_pc<S, decltype(H)::value, decltype(FO)::value, decltype(M)::value, false>), grid,
+                               block, 0, stream, F, B, Fo, Bo, Tf, Tconst, g, k, cd, flag, fg, accel, wsrc);
     };
     using tt = std::true_type;
     using ff = std::false_type;
@@ -75,7 +84,8 @@ template <int S> hipError_t sweep_occupancy(int *per_cu, int *per_cu_pc) {
                                                                 TileFor<S>::type::NT, 0);
     if constexpr (S != 0) {
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_pc, k_fused_pc<S, false, false, false>, PC_THREADS, 0);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu_pc, k_fused_pc<S, false, false, false, false>,
+                                                             PC_THREADS, 0);
     }
     return e;
 }
@@ -87,7 +97,8 @@ template int launch_fused<SW>(const Storage<SW>::T *, const Storage<SW>::T *, St
 #if LBM_SWEEP_S != 0
 template int launch_fused_pc<SW>(const Storage<SW>::T *, const Storage<SW>::T *, Storage<SW>::T *, Storage<SW>::T *,
                                  const Storage<SW>::C *, Storage<SW>::C, const Geo &, const StepConst<Storage<SW>::C> &,
-                                 const Codec &, unsigned *, int, hipStream_t, const Storage<SW>::C *);
+                                 const Codec &, unsigned *, int, hipStream_t, const Storage<SW>::C *,
+                                 const Storage<SW>::C *);
 #endif
 template hipError_t sweep_occupancy<SW>(int *, int *);
 

@@ -23,11 +23,14 @@ int launch_fused(const typename Storage<S>::T *F, const typename Storage<S>::T *
                  bool gathered, int slots, hipStream_t stream, const typename Storage<S>::C *accel = nullptr);
 
 // One step of the producer/consumer sweep (k_fused_pc; S = 1, 2, 3 and B scattered), as above.
+// With walls (g.walls) it steps the interior planes 1 .. nz-2 only and needs wsrc, the source
+// planes (NSRC planes of n values) holding at least planes 0 and nz-1; returns -1 without it.
 template <int S>
 int launch_fused_pc(const typename Storage<S>::T *F, const typename Storage<S>::T *B, typename Storage<S>::T *Fo,
                     typename Storage<S>::T *Bo, const typename Storage<S>::C *Tf, typename Storage<S>::C Tconst,
                     const Geo &g, const StepConst<typename Storage<S>::C> &k, const Codec &cd, unsigned *flag, int slots,
-                    hipStream_t stream, const typename Storage<S>::C *accel = nullptr);
+                    hipStream_t stream, const typename Storage<S>::C *accel = nullptr,
+                    const typename Storage<S>::C *wsrc = nullptr);
 
 // Work-groups of each sweep that one CU holds at once (the runtime's occupancy of the steady-state
 // kernel of storage S); per_cu_pc is left alone for S = 0.

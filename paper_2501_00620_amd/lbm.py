@@ -188,7 +188,9 @@ class Lattice:
     def set_walls(self, u_bottom=None, u_top=None, on=True):
         """Walls normal to z half-way outside planes 0 and nz - 1 (half-way bounce-back), moving
         with the tangential velocities u_bottom and u_top (3-vectors, default at rest); on=False
-        restores the periodic z direction.  Such a lattice steps with the two-pass kernel."""
+        restores the periodic z direction.  A float or 16-bit lattice with walls steps its interior
+        planes in the split fused sweep and its wall planes with the two-pass wall kernel; double
+        precision steps two-pass."""
         if not on:
             _check(_lib.lbm_set_walls(self._h, 0, None, None))
             return

@@ -1,6 +1,7 @@
 """GPU parity of the walls (lbm_set_walls: half-way bounce-back with moving walls, the channels
 of Sec. III A and C) against the oracle, through the C ABI, in the bump scheme and the standard
-comparator, with and without a body force.
+comparator, with and without a body force; the split fused sweep with walls (interior planes in
+the sweep, the wall planes with the two-pass wall kernel) against the two-pass step.
 
 Bars: FP64 storage <= 1e-12 and FP32 <= 1e-5 relative L2 on the state and the moments; exact
 mass conservation and the steady linear Couette profile on the GPU; the Poiseuille viscosity.
@@ -36,7 +37,8 @@ UB, UT = [0.02, -0.01, 0.0], [-0.015, 0.03, 0.0]
 @pytest.mark.parametrize("storage,tol,kernel", [("f64", 1e-12, "auto"), ("f32", 1e-5, "auto"),
                                                 ("f32", 1e-5, "two_pass")])
 def test_walls_parity(dims, mode, force, storage, tol, kernel):
-    # a lattice with walls steps two-pass whatever kernel "auto" would take without them
+    # "auto": FP64 steps two-pass; FP32 steps its interior planes in the split fused sweep (from
+    # the second step on) and its wall planes with the wall kernel
     tau, steps = 0.7, 30
     fields = wl.fourier_fields(*dims, seed=31, u_max=0.2)
     g = lbm().Lattice(*dims, tau, storage=storage, mode=mode, kernel=kernel)
@@ -170,22 +172,26 @@ def test_wall_argument_errors():
         g.set_walls([float("nan"), 0, 0], None)
     g.set_walls()
     with pytest.raises(L.LBMError):
-        g.set_kernel("fused")
+        g.set_kernel("fused")  # the single-role sweep is periodic
+    g.set_kernel("fused_pc")  # the split sweep takes walls
     f = L.Lattice(8, 8, 8, 0.7, storage="f32", kernel="fused")
     with pytest.raises(L.LBMError):
         f.set_walls()
+    d = L.Lattice(8, 8, 8, 0.7, storage="f64")
+    d.set_walls()
+    with pytest.raises(L.LBMError):
+        d.set_kernel("fused_pc")  # double precision steps two-pass
 
 
-@pytest.mark.skip(reason="walls in the split fused sweep are switched off: its wall variant faulted the "
-                         "GPU (memory aperture violation) in its first run, cause not established")
 @pytest.mark.parametrize("dims", [(17, 9, 5), (32, 16, 3), (70, 13, 37)])
 @pytest.mark.parametrize("tau_g", [None, 0.5])
 @pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16dev", 1e-3), ("bf16dev", 1e-2)])
 def test_split_sweep_with_walls_equals_two_pass(dims, tau_g, storage, tol):
-    # Moving walls, a body force and (or not) a ghost rate: the split sweep with the wall planes
-    # apart against the two-pass step, in every storage it takes.  The same arithmetic up to the
-    # order of the gradient sums (the bars of the periodic comparison).  nz = 37 sweeps the 35
-    # interior planes in two z chunks; nz = 3 leaves one interior plane.
+    # Moving walls, a body force and (or not) a ghost rate: the split sweep over the interior
+    # planes (the wall planes with the wall kernel) against the two-pass step, in every storage it
+    # takes.  The same arithmetic up to the order of the gradient sums (the bars of the periodic
+    # comparison).  nz = 37 sweeps the 35 interior planes in two z chunks; nz = 3 leaves one
+    # interior plane, nz = 5 three.
     fields = wl.fourier_fields(*dims, seed=41, u_max=0.2)
     _, a, _ = wl.fourier_fields(*dims, seed=42, u_max=1.0)
     a = 2e-4 * a + np.array([0.0, 0.0, -1e-3]).reshape(3, 1, 1, 1)
@@ -205,8 +211,6 @@ def test_split_sweep_with_walls_equals_two_pass(dims, tau_g, storage, tol):
     assert rel_l2(out[1][1], out[0][1]) <= tol, rel_l2(out[1][1], out[0][1])
 
 
-@pytest.mark.skip(reason="walls in the split fused sweep are switched off: its wall variant faulted the "
-                         "GPU (memory aperture violation) in its first run, cause not established")
 def test_split_sweep_wall_channel_mass_and_couette():
     # FP32 Couette channel in the split sweep: exact mass conservation with walls at rest, and the
     # steady linear profile between a wall at rest and one moving at U (the two-pass bar)
