@@ -241,7 +241,9 @@ template <int S> struct TwoPass {
                            count);
     }
     // The wall planes 0 and nz-1, stepped with the wall kernel, and the sources of the planes
-    // next to them (which the split sweep's gradients of planes 1 and nz-2 read too).
+    // next to them (which the split sweep's gradients of planes 1 and nz-2 read too).  For a
+    // state whose bbar is held scattered: the split sweep's steps, never the first after
+    // set_fields / set_state.
     template <bool M> void wall_planes() const {
         const int nz = h->p.nz;
         if (nz <= 6) {
