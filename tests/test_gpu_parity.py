@@ -517,14 +517,16 @@ def test_fp16_overflow_is_reported_as_range(kernel):
     assert g.health()[:2] == (0, 0)
 
 
+@pytest.mark.parametrize("walls", [False, True])
 @pytest.mark.parametrize("dims", [(5, 3, 3), (64, 8, 3), (65, 9, 4), (130, 17, 5)])
 @pytest.mark.parametrize("mode", ["thermal", "iso"])
-def test_split_sweep_all_terms_against_oracle(dims, mode):
+def test_split_sweep_all_terms_against_oracle(dims, mode, walls):
     # The split sweep with every term at once, FP32 against the oracle (<= 1e-5): references
-    # shifted off rho = 1, T = 1/3 (the K e_i terms), a body-force field and a ghost rate.  The
-    # shapes take one plane per z chunk past the warm-up (nz = 3, 4, 5), lattices narrower than
-    # the 64 x 8 tile (its lanes wrap onto the same sites and store nothing), one exact tile, and
-    # ragged tiles in x and y.
+    # shifted off rho = 1, T = 1/3 (the K e_i terms), a body-force field and a ghost rate, and
+    # (or not) moving walls, whose planes the wall kernel steps.  The shapes take one plane per z
+    # chunk past the warm-up (nz = 3, 4, 5; with walls one to three interior planes), lattices
+    # narrower than the 64 x 8 tile (its lanes wrap onto the same sites and store nothing), one
+    # exact tile, and ragged tiles in x and y.
     tau, tau_g, steps = 0.7, 0.55, 12
     rho, u, T = wl.fourier_fields(*dims, seed=47, u_max=0.2, T0=0.3)
     rho = 0.8 * rho
@@ -539,6 +541,10 @@ def test_split_sweep_all_terms_against_oracle(dims, mode):
     o = oracle.OracleLattice(nx, ny, nz, tau, mode=mode, tau_ghost=tau_g)
     o.init(rho, u, T)
     o.set_body_force(a)
+    if walls:
+        ub, ut = [0.02, -0.01, 0.0], [-0.015, 0.03, 0.0]
+        g.set_walls(ub, ut)
+        o.set_walls(ub, ut)
     g.step(steps)
     o.step(steps)
-    compare(g, o, 1e-5, f"split sweep, all terms, {dims} {mode}")
+    compare(g, o, 1e-5, f"split sweep, all terms, {dims} {mode}, walls {walls}")
