@@ -81,6 +81,20 @@ def traffic_from_profiles(kernel, workload, launch_sites):
     return rec.get("bytes_per_launch")
 
 
+def valu_busy_from_profiles(kernel, workload):
+    """Share of a SIMD's cycles that issue VALU work in the profiled kernel (wave64 instructions
+    at 4 cycles each over the 1,024 SIMDs, against GRBM_GUI_ACTIVE summed over the 8 XCDs), from
+    committed SQ counters taken on the current sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sq = rec.get("sq") or {}
+    if rec.get("source_hash") != source_hash() or not sq.get("GRBM_GUI_ACTIVE"):
+        return None
+    return sq["SQ_INSTS_VALU"] * 4 / 1024 / (sq["GRBM_GUI_ACTIVE"] / 8)
+
+
 def step_kernel(kernel, storage, nz):
     """The kernel that times the steady-state steps of an n^3 lattice (lbm_set_kernel's choice)."""
     if kernel == "two_pass":
@@ -154,8 +168,14 @@ def run_variants(n, steps, tau, mach, every=500):
             ke.append(float((0.5 * r * (u * u).sum(0)).sum() / r.sum()))
         r, u, T = lat.moments()
         bad = lat.health()
-        rec = {"mlups": n ** 3 * steps / t_total / 1e6, "kinetic_energy": ke,
+        mlups = n ** 3 * steps / t_total / 1e6
+        gbs = mlups * VALUES_PER_LUP * BYTES_PER_VALUE[storage] / 1e3
+        rec = {"mlups": mlups, "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS, "kinetic_energy": ke,
                "nonfinite_sites": bad[0]}
+        if n == 256:
+            busy = valu_busy_from_profiles(step_kernel("auto", storage, n), "tgv256_" + storage)
+            if busy is not None:
+                rec["valu_issue_busy"] = busy
         if ref is None:
             ref = (r, u, T)
         else:
