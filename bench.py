@@ -653,8 +653,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the sweep has no multi-GPU path in this build "
-              "(domain decomposition is design-only); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the sweep has no multi-GPU path (a z-slab decomposition "
+              "is designed, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
