@@ -207,6 +207,11 @@ def run_serving(storage, n_requests=512, rate=50.0, steps=2000, budget=4 << 30, 
         times = np.array([srv.poll(r)[1:] for r in ids])
         errors = [srv.error(r) if s_ != "done" else "" for r, s_ in zip(ids, status)]
         st = srv.stats()
+        # results of every 8th request, fetched after the timed run, for the storages' comparison
+        sample = {}
+        for k, (r, s_) in enumerate(zip(ids, status)):
+            if s_ == "done" and k % 8 == 0:
+                sample[k] = tuple(np.asarray(a, np.float32) for a in srv.fetch(r))
     ok = np.array([s_ == "done" for s_ in status])
     print(f"[bench] served {storage}: {int(ok.sum())}/{n_requests} done", file=sys.stderr, flush=True)
     latency = times[:, 2] - times[:, 0]
@@ -226,7 +231,7 @@ def run_serving(storage, n_requests=512, rate=50.0, steps=2000, budget=4 << 30, 
            "bundle_busy_mlups": st["lattice_updates"] / max(st["busy_s"], 1e-9) / 1e6,
            "workload": f"{n_requests} four-quadrant Riemann problems n x n x 1, n ~ U[64,512], tau {tau}, "
                        f"{steps} steps, Poisson {rate}/s, budget {budget / 2**30:.0f} GiB, bundle {bundle} steps"}
-    return rec, ok, latency
+    return rec, ok, latency, sample
 
 
 def run_served_comparison(storages=("f32", "f16dev", "bf16dev"), **kw):
@@ -234,18 +239,33 @@ def run_served_comparison(storages=("f32", "f16dev", "bf16dev"), **kw):
     ones do depends on the storage precision, so beside each run's own percentiles the latency is
     also given over the requests that completed under every storage."""
     import numpy as np
-    out, oks, lats = {}, [], []
+    out, oks, lats, samples = {}, [], [], []
     for st in storages:
-        rec, ok, lat = run_serving(st, **kw)
+        rec, ok, lat, sample = run_serving(st, **kw)
         out[st] = rec
         oks.append(ok)
         lats.append(lat)
+        samples.append(sample)
     common = np.logical_and.reduce(oks)
-    for st, ok, lat in zip(storages, oks, lats):
+    for st, ok, lat, sample in zip(storages, oks, lats, samples):
         out[st]["failed_also_in_" + storages[0]] = int((~ok & ~oks[0]).sum())
         out[st]["common_requests"] = int(common.sum())
         out[st]["p50_s_common"] = float(np.percentile(lat[common], 50))
         out[st]["p99_s_common"] = float(np.percentile(lat[common], 99))
+        if st == storages[0]:
+            continue
+        # the served results against the first storage's, request by request (every 8th request
+        # that both completed): the error a lower-precision storage adds to what it serves
+        keys = sorted(set(sample) & set(samples[0]))
+        errs = {f: [] for f in ("rho", "u", "T")}
+        for k in keys:
+            for f, a, b in zip(("rho", "u", "T"), sample[k], samples[0][k]):
+                a64, b64 = a.astype(np.float64), b.astype(np.float64)
+                errs[f].append(float(np.linalg.norm(a64 - b64) / np.linalg.norm(b64)))
+        if keys:
+            out[st]["rel_l2_vs_" + storages[0]] = {
+                "sampled_requests": len(keys),
+                **{f: {"median": float(np.median(v)), "max": float(np.max(v))} for f, v in errs.items()}}
     return out
 
 
