@@ -398,6 +398,23 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
         // One iteration with A0, A1, A2 the sums of planes q-1, q, q+1; A0 is then done and
         // serves as the next iteration's plane q+2, whose first term sets it (gradt_set).  Rotating
         // the roles by argument order (the loop unrolled by three) moves no registers.
+        // The populations of the plane a consumer collides, read a second time (their last use:
+        // non-temporal in single precision), at the top priority, above the ring producers, then
+        // back to the consumers' level: in float and BF16 storage the chain the collision waits
+        // on starts earlier (+3% / +2%); FP16 storage measured -0.5% and keeps its level.  In
+        // single precision they are loaded one iteration ahead, after the previous plane's
+        // stores (loop-carried, no extra registers: +2.5%); in 16-bit storage that costs 5%, and
+        // they are loaded at the start of their own iteration.
+        constexpr int POL = S == 1 ? 2 : 0;
+        constexpr bool AHEAD = S == 1;
+        constexpr bool LOAD_FIRST = S != 2;
+        R craw[Q];
+        auto craw_issue = [&](int zl) {  // zl: the plane's offset in sites
+            if constexpr (LOAD_FIRST) __builtin_amdgcn_s_setprio(3);
+            Unroll<0, Q>::run([&](auto I) { craw[I] = bF.template loadraw<I, POL>(ixy * SB, zl * SB); });
+            if constexpr (LOAD_FIRST) __builtin_amdgcn_s_setprio(1);
+        };
+        if constexpr (AHEAD) craw_issue(zoff(z0));
         auto iter = [&](int p, GradT<C> &A0, GradT<C> &A1, GradT<C> &A2) {
             const int q = p - 1;  // the source plane the producers finished last iteration
             if (q >= z0 - 1) {
@@ -405,20 +422,11 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                 // plane q-1 is one of the chunk's (wave-uniform); its lanes outside the lattice
                 // compute on the wrapped site and store nothing
                 const bool live = q - 1 >= z0;
-                // the populations of plane q-1, read again for its collision (their last use:
-                // non-temporal in single precision).  The chunk's first iteration, which has no
-                // plane to collide, loads the plane the producers read first (an L2 hit) and
-                // discards it: a value defined on every path costs no register fill.
-                constexpr int POL = S == 1 ? 2 : 0;
-                const int zl = live ? zc : zoff(z0 - 1);
-                // issued at the top priority, above the ring producers, then back to the
-                // consumers' level: in float and BF16 storage the chain the collision waits on
-                // starts earlier (+3% / +2%); FP16 storage measured -0.5% and keeps its level
-                constexpr bool LOAD_FIRST = S != 2;
-                R craw[Q];
-                if constexpr (LOAD_FIRST) __builtin_amdgcn_s_setprio(3);
-                Unroll<0, Q>::run([&](auto I) { craw[I] = bF.template loadraw<I, POL>(ixy * SB, zl * SB); });
-                if constexpr (LOAD_FIRST) __builtin_amdgcn_s_setprio(1);
+                // 16-bit storage: the populations of plane q-1 now.  The chunk's first
+                // iteration, which has no plane to collide, loads the plane the producers read
+                // first (an L2 hit) and discards it: a value defined on every path costs no
+                // register fill.
+                if constexpr (!AHEAD) craw_issue(live ? zc : zoff(z0 - 1));
                 // source plane q: its 3 x 3 neighbourhood adds to the sums of planes q-1, q, q+1
                 const C *pl = lsrc[cslot(q)] + iidx;
                 Unroll<0, 9>::run([&](auto O) {
@@ -487,6 +495,9 @@ k_fused_pc(const typename Storage<S>::T *__restrict__ F, const typename Storage<
                             [&](auto c) { bBo.template storef<c, Q>(ixy * SB, cur.beta[c], cd, amax, zc * SB); });
                     }
                 }
+                // single precision: the populations of plane q, collided next iteration (past the
+                // chunk's end its last plane again, unused)
+                if constexpr (AHEAD) craw_issue(zoff(min(max(q, z0), z1 - 1)));
             }
             __syncthreads();
         };
